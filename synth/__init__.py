@@ -1,0 +1,381 @@
+"""Seeded synthetic inputs for GP population evaluation.
+
+This module only draws random programs and random data: it builds prefix
+trees, linear register programs, feature-major case matrices, noise and the
+labels of a linear model.  It evaluates no GP program; target values that come
+from a program are computed by whichever evaluator the caller owns.
+
+Program formats (the public interchange format of the evaluation library):
+
+* Prefix trees: ``tok`` int32, opcode in the low 8 bits and, for a variable,
+  the feature index in the high 24 bits; ``cst`` float32 parallel to ``tok``
+  (the value of a constant token, 0 elsewhere); ``off`` int64 CSR offsets,
+  program ``p`` is ``tok[off[p]:off[p+1]]``.
+* Linear register programs: ``code`` uint32 words ``op | dst<<8 | src1<<16 |
+  src2<<24``; a source id below ``n_reg`` is a register, ids in
+  ``[n_reg, n_reg+n_feat)`` are features, ids in ``[128, 256)`` index the
+  program's constant table ``cst[cst_off[p] + id-128]``.
+
+Every generator takes an explicit ``numpy.random.Generator`` (PCG64) so that
+the GPU path, the oracle and the benchmark see identical arrays.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+# Opcodes of the interchange format.
+ADD, SUB, MUL, PDIV, SIN, COS, EXPC, PLOG = 0, 1, 2, 3, 4, 5, 6, 7
+VAR, CONST = 64, 65
+ARITY = {ADD: 2, SUB: 2, MUL: 2, PDIV: 2, SIN: 1, COS: 1, EXPC: 1, PLOG: 1}
+NAMES = {ADD: "+", SUB: "-", MUL: "*", PDIV: "/", SIN: "sin", COS: "cos",
+         EXPC: "exp", PLOG: "log"}
+BASIC = (ADD, SUB, MUL, PDIV)
+FULL = (ADD, SUB, MUL, PDIV, SIN, COS, EXPC, PLOG)
+ARITH3 = (ADD, SUB, MUL)
+
+SRC_CONST_BASE = 128
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ----------------------------------------------------------------------------
+# Program containers
+# ----------------------------------------------------------------------------
+@dataclass
+class TreePop:
+    tok: np.ndarray            # int32
+    cst: np.ndarray            # float32
+    off: np.ndarray            # int64, len P+1
+
+    @property
+    def n_prog(self) -> int:
+        return len(self.off) - 1
+
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.off)
+
+    def program(self, p: int):
+        a, b = int(self.off[p]), int(self.off[p + 1])
+        return self.tok[a:b], self.cst[a:b]
+
+    def subset(self, idx) -> "TreePop":
+        return trees_from_lists([self.program(int(i)) for i in idx])
+
+
+@dataclass
+class LinearPop:
+    code: np.ndarray           # uint32
+    off: np.ndarray            # int64, len P+1
+    cst: np.ndarray            # float32
+    cst_off: np.ndarray        # int64, len P+1
+    n_reg: int = 8
+
+    @property
+    def n_prog(self) -> int:
+        return len(self.off) - 1
+
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.off)
+
+    def subset(self, idx) -> "LinearPop":
+        code, cst = [], []
+        for i in idx:
+            i = int(i)
+            code.append(self.code[self.off[i]:self.off[i + 1]])
+            cst.append(self.cst[self.cst_off[i]:self.cst_off[i + 1]])
+        return linear_from_lists(code, cst, self.n_reg)
+
+
+def trees_from_lists(progs) -> TreePop:
+    """progs: iterable of (tok, cst) pairs."""
+    toks, csts, off = [], [], [0]
+    for t, c in progs:
+        t = np.asarray(t, dtype=np.int32)
+        c = np.asarray(c, dtype=np.float32)
+        toks.append(t)
+        csts.append(c)
+        off.append(off[-1] + len(t))
+    tok = np.concatenate(toks) if toks else np.zeros(0, np.int32)
+    cst = np.concatenate(csts) if csts else np.zeros(0, np.float32)
+    return TreePop(tok.astype(np.int32), cst.astype(np.float32),
+                   np.asarray(off, dtype=np.int64))
+
+
+def linear_from_lists(codes, csts, n_reg: int = 8) -> LinearPop:
+    off, coff = [0], [0]
+    for c, k in zip(codes, csts):
+        off.append(off[-1] + len(c))
+        coff.append(coff[-1] + len(k))
+    code = np.concatenate([np.asarray(c, np.uint32) for c in codes]) if codes else np.zeros(0, np.uint32)
+    cst = np.concatenate([np.asarray(k, np.float32) for k in csts]) if csts else np.zeros(0, np.float32)
+    return LinearPop(code.astype(np.uint32), np.asarray(off, np.int64),
+                     cst.astype(np.float32), np.asarray(coff, np.int64), n_reg)
+
+
+def var_tok(k: int) -> int:
+    return VAR | (k << 8)
+
+
+def lin_word(op: int, dst: int, s1: int, s2: int) -> int:
+    return (op & 0xFF) | ((dst & 0xFF) << 8) | ((s1 & 0xFF) << 16) | ((s2 & 0xFF) << 24)
+
+
+# ----------------------------------------------------------------------------
+# Tree generators
+# ----------------------------------------------------------------------------
+def _terminal(rng, n_feat, p_const, crange):
+    if rng.random() < p_const:
+        return CONST, np.float32(rng.uniform(crange[0], crange[1]))
+    return var_tok(int(rng.integers(n_feat))), np.float32(0.0)
+
+
+def _grow_full(rng, depth, full, fset, n_feat, p_const, crange, out_t, out_c):
+    # Prefix emission.  Depth 0 means "a terminal here".
+    n_fun = len(fset)
+    if depth == 0:
+        t, c = _terminal(rng, n_feat, p_const, crange)
+        out_t.append(t); out_c.append(c)
+        return
+    if not full:
+        # grow: any primitive, terminals weighted by the size of the terminal set
+        n_term = n_feat + (1 if p_const > 0 else 0)
+        if rng.random() < n_term / (n_term + n_fun):
+            t, c = _terminal(rng, n_feat, p_const, crange)
+            out_t.append(t); out_c.append(c)
+            return
+    f = fset[int(rng.integers(n_fun))]
+    out_t.append(f); out_c.append(np.float32(0.0))
+    for _ in range(ARITY[f]):
+        _grow_full(rng, depth - 1, full, fset, n_feat, p_const, crange, out_t, out_c)
+
+
+def random_tree(rng, depth, full, fset, n_feat, p_const, crange=(-1.0, 1.0)):
+    t, c = [], []
+    _grow_full(rng, depth, full, fset, n_feat, p_const, crange, t, c)
+    return np.asarray(t, np.int32), np.asarray(c, np.float32)
+
+
+def ramped_half_and_half(rng, n, fset, n_feat, dmin, dmax, max_nodes,
+                         p_const=0.5, crange=(-1.0, 1.0)) -> TreePop:
+    """Koza's ramped half-and-half: depths cycle over [dmin, dmax], alternate
+    grow and full; trees larger than max_nodes are re-drawn."""
+    progs = []
+    depths = list(range(dmin, dmax + 1))
+    i = 0
+    while len(progs) < n:
+        d = depths[(i // 2) % len(depths)]
+        full = (i % 2) == 1
+        i += 1
+        t, c = random_tree(rng, d, full, fset, n_feat, p_const, crange)
+        if len(t) > max_nodes:
+            continue
+        progs.append((t, c))
+    return trees_from_lists(progs)
+
+
+def ptc2_tree(rng, target, fset, n_feat, p_const, crange=(-1.0, 1.0)):
+    """Luke's PTC2 size-targeted growth: expand randomly chosen open argument
+    slots with functions until the node count plus the open slots reaches the
+    target, then close every open slot with a terminal.  Returns prefix arrays
+    with at most ``target`` nodes (a single terminal when target == 1)."""
+    if target <= 1:
+        t, c = _terminal(rng, n_feat, p_const, crange)
+        return np.asarray([t], np.int32), np.asarray([c], np.float32)
+    # node records: (op, children list)
+    ops = []
+    kids = []
+    open_slots = []           # (parent, position)
+    def new_fun(f):
+        ops.append(f)
+        kids.append([-1] * ARITY[f])
+        idx = len(ops) - 1
+        for pos in range(ARITY[f]):
+            open_slots.append((idx, pos))
+        return idx
+
+    roots = [g for g in fset if 1 + ARITY[g] <= target]
+    if not roots:
+        t, c = _terminal(rng, n_feat, p_const, crange)
+        return np.asarray([t], np.int32), np.asarray([c], np.float32)
+    new_fun(roots[int(rng.integers(len(roots)))])
+    n_nodes = 1
+    while open_slots:
+        # a function added at an open slot grows the final size by its arity
+        choices = [g for g in fset if n_nodes + len(open_slots) + ARITY[g] - 1 + 1 <= target]
+        if n_nodes + len(open_slots) >= target or not choices:
+            break
+        j = int(rng.integers(len(open_slots)))
+        parent, pos = open_slots[j]
+        open_slots[j] = open_slots[-1]
+        open_slots.pop()
+        g = choices[int(rng.integers(len(choices)))]
+        child = new_fun(g)
+        kids[parent][pos] = child
+        n_nodes += 1
+    for parent, pos in open_slots:
+        t, c = _terminal(rng, n_feat, p_const, crange)
+        ops.append(("T", t, c))
+        kids.append([])
+        kids[parent][pos] = len(ops) - 1
+    # prefix emission (iterative)
+    out_t, out_c = [], []
+    stack = [0]
+    while stack:
+        i = stack.pop()
+        o = ops[i]
+        if isinstance(o, tuple):
+            out_t.append(o[1]); out_c.append(o[2])
+        else:
+            out_t.append(o); out_c.append(np.float32(0.0))
+            for ch in reversed(kids[i]):
+                stack.append(ch)
+    return np.asarray(out_t, np.int32), np.asarray(out_c, np.float32)
+
+
+def ptc2_population(rng, n, fset, n_feat, size_lo, size_hi, p_const,
+                    crange=(-1.0, 1.0), sizes=None) -> TreePop:
+    progs = []
+    for i in range(n):
+        target = int(sizes[i]) if sizes is not None else int(rng.integers(size_lo, size_hi + 1))
+        progs.append(ptc2_tree(rng, target, fset, n_feat, p_const, crange))
+    return trees_from_lists(progs)
+
+
+# ----------------------------------------------------------------------------
+# Linear register programs
+# ----------------------------------------------------------------------------
+def linear_population(rng, n, len_lo, len_hi, ops, n_reg, n_feat, n_const=0,
+                      crange=(-1.0, 1.0), lengths=None) -> LinearPop:
+    """dst uniform over registers; sources uniform over registers, features
+    and (if n_const > 0) the program's constants."""
+    codes, csts = [], []
+    n_src = n_reg + n_feat + n_const
+    ops = np.asarray(ops, np.uint32)
+    for i in range(n):
+        L = int(lengths[i]) if lengths is not None else int(rng.integers(len_lo, len_hi + 1))
+        op = ops[rng.integers(len(ops), size=L)]
+        dst = rng.integers(n_reg, size=L).astype(np.uint32)
+        s = rng.integers(n_src, size=(2, L)).astype(np.uint32)
+        s = np.where(s >= n_reg + n_feat, s - (n_reg + n_feat) + SRC_CONST_BASE, s)
+        code = op | (dst << 8) | (s[0] << 16) | (s[1] << 24)
+        codes.append(code.astype(np.uint32))
+        csts.append(rng.uniform(crange[0], crange[1], size=n_const).astype(np.float32))
+    return linear_from_lists(codes, csts, n_reg)
+
+
+# ----------------------------------------------------------------------------
+# Case matrices and targets
+# ----------------------------------------------------------------------------
+def uniform_cases(rng, n_feat, n_cases, lo, hi) -> np.ndarray:
+    """Feature-major float32 matrix X[f, c]."""
+    return rng.uniform(lo, hi, size=(n_feat, n_cases)).astype(np.float32)
+
+
+def normal_cases(rng, n_feat, n_cases) -> np.ndarray:
+    return rng.standard_normal(size=(n_feat, n_cases)).astype(np.float32)
+
+
+def gaussian_noise(rng, n_cases, sigma) -> np.ndarray:
+    return (rng.standard_normal(n_cases) * sigma).astype(np.float32)
+
+
+def sign_labels(rng, X: np.ndarray):
+    """Labels of a random linear model: w ~ N(0,1)^F; s = w0*x0 + w1*x1 + ...
+    accumulated left to right in float32 (each product and each sum rounded
+    to binary32); label +1 where s > 0, else -1.  Returns (w, y)."""
+    F = X.shape[0]
+    w = rng.standard_normal(F).astype(np.float32)
+    s = np.zeros(X.shape[1], np.float32)
+    for f in range(F):
+        s = (s + (w[f] * X[f]).astype(np.float32)).astype(np.float32)
+    y = np.where(s > np.float32(0.0), np.float32(1.0), np.float32(-1.0)).astype(np.float32)
+    return w, y
+
+
+def lognormal_lengths(rng, n, mu, sigma, lo, hi) -> np.ndarray:
+    v = np.rint(rng.lognormal(mu, sigma, size=n))
+    return np.clip(v, lo, hi).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# Workloads (the paper-shaped synthetic configurations)
+# ----------------------------------------------------------------------------
+@dataclass
+class TreeWorkload:
+    name: str
+    pop: TreePop
+    X: np.ndarray              # (F, N) float32
+    target: TreePop            # candidate target trees, first acceptable one is used
+    noise: np.ndarray          # (N,) float32 added to the target values
+    kind: str                  # "sum_abs" | "mse" | "hits"
+    fset: tuple
+    meta: dict = field(default_factory=dict)
+
+
+@dataclass
+class LinearWorkload:
+    name: str
+    pop: LinearPop
+    X: np.ndarray
+    y: np.ndarray
+    kind: str
+    meta: dict = field(default_factory=dict)
+
+
+def tiny_tree_workload(seed: int = 1, n_prog: int = 100, n_cases: int = 1024) -> TreeWorkload:
+    """100 ramped half-and-half trees (depth 2-6, <=64 nodes) over {+,-,*,/p},
+    terminals {x0, U(-1,1) constant} with probability 1/2 each; 1024 cases
+    x0 ~ U(-1,1); target values from one full depth-5 tree; sum |error|."""
+    rng = rng_for(seed)
+    pop = ramped_half_and_half(rng, n_prog, BASIC, 1, 2, 6, 64, p_const=0.5)
+    X = uniform_cases(rng, 1, n_cases, -1.0, 1.0)
+    tt, tc = random_tree(rng, 5, True, BASIC, 1, 0.5)
+    target = trees_from_lists([(tt, tc)])
+    return TreeWorkload("tiny-tree-100x1024", pop, X, target,
+                        np.zeros(n_cases, np.float32), "sum_abs", BASIC,
+                        dict(n_feat=1, n_cases=n_cases, n_prog=n_prog))
+
+
+def scale_tree_workload(seed: int = 2, n_prog: int = 4096, n_cases: int = 65536,
+                        n_feat: int = 8, fset=FULL, max_size: int = 256,
+                        n_target_candidates: int = 16) -> TreeWorkload:
+    """4096 PTC2 trees of size U{1..256} over the given function set,
+    terminals x0..x7 and a U(-1,1) constant drawn uniformly among the nine;
+    cases X ~ U(-5,5) feature-major; target = first candidate tree whose
+    values are all finite with |y| < 1e6, plus N(0, sigma=0.01) noise; MSE."""
+    rng = rng_for(seed)
+    p_const = 1.0 / (n_feat + 1)
+    pop = ptc2_population(rng, n_prog, fset, n_feat, 1, max_size, p_const)
+    X = uniform_cases(rng, n_feat, n_cases, -5.0, 5.0)
+    cands = [ptc2_tree(rng, int(rng.integers(8, 33)), fset, n_feat, p_const)
+             for _ in range(n_target_candidates)]
+    target = trees_from_lists(cands)
+    noise = gaussian_noise(rng, n_cases, 0.01)
+    name = "scale-tree-%dx%d-F%d-%s" % (n_prog, n_cases, n_feat,
+                                        "full" if tuple(fset) == FULL else "arith")
+    return TreeWorkload(name, pop, X, target, noise, "mse", tuple(fset),
+                        dict(n_feat=n_feat, n_cases=n_cases, n_prog=n_prog))
+
+
+def linear_workload(seed: int = 3, n_prog: int = 4096, n_cases: int = 1 << 20,
+                    n_reg: int = 8, n_feat: int = 16, len_lo: int = 32,
+                    len_hi: int = 256) -> LinearWorkload:
+    """4096 register programs of U{32..256} instructions over {+,-,*,/p},
+    dst uniform over 8 registers, sources uniform over the 24 register and
+    feature ids, no constants; X ~ N(0,1); labels = sign of a random linear
+    model; fitness = hit count."""
+    rng = rng_for(seed)
+    pop = linear_population(rng, n_prog, len_lo, len_hi, BASIC, n_reg, n_feat)
+    X = normal_cases(rng, n_feat, n_cases)
+    w, y = sign_labels(rng, X)
+    return LinearWorkload("linear-%dx%d-R%d-F%d" % (n_prog, n_cases, n_reg, n_feat),
+                          pop, X, y, "hits", dict(w=w, n_feat=n_feat, n_cases=n_cases))
+
+
+def wl_scaled_tree(seed, n_prog, n_cases, n_feat=8, fset=FULL, max_size=256):
+    return scale_tree_workload(seed, n_prog, n_cases, n_feat, fset, max_size)
