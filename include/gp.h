@@ -1,0 +1,181 @@
+/*
+ * gp.h -- C ABI of the MI355X (gfx950) genetic-programming population
+ * evaluator.
+ *
+ * What it computes.  For every candidate program p and every fitness case c
+ * the library runs p on row c of a feature-major case matrix and reduces the
+ * per-case errors to one fitness value per program.  This is the evaluation
+ * phase of GP, the part of a GP run the paper accelerates: every program is
+ * interpreted over every fitness case (sections 1, 3 and 4), and the paper's
+ * two-dimensional stack applies each decoded instruction to a whole tile of
+ * cases at once (section 4, Figure 1).  Trees are lowered on the host to the
+ * paper's stack-operand linear form (operands X = case input, C = constant,
+ * S = top of stack; section 5); register linear programs (dst, op, src1,
+ * src2) are evaluated directly.
+ *
+ * Conventions shared by every entry point.
+ *   - Return value: GP_OK (0) or a negative gp_status; gp_last_error() then
+ *     holds a message for the calling thread.
+ *   - Case data: X is DEVICE memory, float32, feature-major: the value of
+ *     feature f on case c is X[f * n_cases + c].  y (targets or labels) is
+ *     DEVICE memory, float32[n_cases].  Neither is copied; the caller keeps
+ *     them alive until the stream has passed the call.
+ *   - Programs are HOST memory (a GP run breeds them on the host); the
+ *     library validates, lowers and copies them into its own buffers before
+ *     the call returns, so the caller may reuse them at once.
+ *   - out is DEVICE memory: float[n_prog] for GP_FIT_SUM_ABS and GP_FIT_MSE,
+ *     int32[n_prog] for GP_FIT_HITS, float[n_prog * n_cases] (row p holds
+ *     program p's outputs) for GP_OUT_CASES.
+ *   - stream is a hipStream_t (NULL = the null stream).  Calls are stream
+ *     ordered and asynchronous: out is valid once the stream has passed the
+ *     call.  Library scratch (lowered programs, per-tile partial sums) is
+ *     owned by the library and reused in stream order.
+ *   - Arithmetic: IEEE binary32, round to nearest even, no contraction,
+ *     denormals kept.  pdiv(a,b) = |b| < 1e-6f ? 1 : a/b; plog(a) =
+ *     |a| < 1e-6f ? 0 : log|a|; expc(a) = exp(min(a, 88)) with NaN passing
+ *     through; sin/cos/exp/log are evaluated in binary64 by the device math
+ *     library and rounded once to binary32 (within 2 ulp of the exact value,
+ *     and almost always the correctly rounded one).  The paper names these
+ *     functions without defining their protection.
+ *   - Fitness: d = out - y in binary32; sum of |d|, mean of d*d, or the
+ *     number of cases with (out > 0) == (y > 0) (Table 2: mean squared error
+ *     for regression, a count of classifications for classification).  Sums
+ *     are accumulated in binary64 and rounded to binary32 once.
+ */
+#ifndef GP_H_
+#define GP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GP_OK = 0,
+    GP_E_INVAL = -1,    /* malformed program, index out of range, null pointer, n_cases < 1, bad kind */
+    GP_E_NOMEM = -2,    /* allocation failed, or a request can never fit a server's memory budget */
+    GP_E_DEPTH = -3,    /* a program needs more stack levels or instructions than supported */
+    GP_E_DEVICE = -4,   /* a HIP call failed; its message is in gp_last_error() */
+    GP_E_AGAIN = -5,    /* a server queue is full */
+    GP_E_NOTFOUND = -6, /* unknown dataset or ticket */
+    GP_E_TIMEOUT = -7   /* a wait ran out of time */
+} gp_status;
+
+typedef enum {
+    GP_FIT_SUM_ABS = 0,
+    GP_FIT_MSE = 1,
+    GP_FIT_HITS = 2,
+    GP_OUT_CASES = 3
+} gp_fitness_kind;
+
+/* Opcodes.  Tree token: low 8 bits = opcode, high 24 bits = feature index
+ * for GP_VAR.  Linear word: op | dst << 8 | src1 << 16 | src2 << 24. */
+enum {
+    GP_ADD = 0, GP_SUB = 1, GP_MUL = 2, GP_PDIV = 3,
+    GP_SIN = 4, GP_COS = 5, GP_EXPC = 6, GP_PLOG = 7,
+    GP_VAR = 64, GP_CONST = 65
+};
+
+/* Linear source ids: [0, n_reg) registers, [n_reg, n_reg + n_feat) features,
+ * [GP_SRC_CONST, 256) the program's constants. */
+#define GP_SRC_CONST 128
+#define GP_MAX_REG 8          /* registers of a linear program */
+#define GP_MAX_FEAT 32        /* features per case matrix */
+#define GP_MAX_DEPTH 12       /* stack levels of a lowered tree */
+#define GP_MAX_LEN 65536      /* instructions (tree nodes) per program */
+
+/* ------------------------------------------------------------------------ */
+/* One-shot evaluation                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Evaluate n_prog prefix trees.  tok/cst/off are HOST arrays in CSR form:
+ * program p is tok[off[p] .. off[p+1]) with cst[i] the value of constant
+ * token i.  Each tree is validated (arity, feature index < n_feat), lowered
+ * to the stack-operand form with the deeper subtree evaluated first
+ * (Sethi-Ullman order, which bounds the stack depth by log2 of the leaf
+ * count) and run by the two-dimensional-stack kernel. */
+gp_status gp_eval_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog,
+                       const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                       int32_t kind, void* out, void* stream);
+
+/* Evaluate n_prog register linear programs over n_reg registers.  code/off
+ * are HOST arrays in CSR form; cst/cst_off (HOST, may be NULL when no
+ * program uses a constant) hold each program's constant table.  Registers
+ * start as r[k] = x[k mod n_feat]; the output is r[0]; unary functions read
+ * src1 only. */
+gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* cst,
+                         const int64_t* cst_off, int32_t n_prog, int32_t n_reg,
+                         const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                         int32_t kind, void* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Resident program sets: lower and upload once, evaluate many times        */
+/* (a GP generation evaluated on several datasets, or timed repeatedly).    */
+/* ------------------------------------------------------------------------ */
+typedef struct gp_progset gp_progset;
+
+typedef struct {
+    int32_t n_prog;
+    int32_t form;              /* 0 = tree, 1 = linear */
+    int32_t n_feat;            /* features the programs may read */
+    int32_t max_depth;         /* stack levels needed (trees) */
+    int64_t n_instr;           /* device instructions over all programs */
+    int64_t n_gpop;            /* GP operations per fitness case: tree nodes, or linear instructions */
+} gp_progset_info;
+
+/* Same program arguments as gp_eval_tree / gp_eval_linear.  The upload is
+ * stream ordered on `stream`; *ps is owned by the caller until
+ * gp_progset_destroy. */
+gp_status gp_progset_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog,
+                          int32_t n_feat, void* stream, gp_progset** ps);
+gp_status gp_progset_linear(const uint32_t* code, const int64_t* off, const float* cst,
+                            const int64_t* cst_off, int32_t n_prog, int32_t n_reg, int32_t n_feat,
+                            void* stream, gp_progset** ps);
+/* Evaluate a resident set on a case matrix with n_feat >= the set's n_feat. */
+gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases,
+                          const float* y, int32_t kind, void* out, void* stream);
+gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info);
+/* Waits for the device to finish with the set, then frees it. */
+gp_status gp_progset_destroy(gp_progset* ps);
+
+/* ------------------------------------------------------------------------ */
+/* Host-side lowering, exposed for inspection and tests (no GPU needed).    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_nodes;           /* tree nodes (GP operations per case) */
+    int32_t n_instr;           /* stack-operand instructions after lowering */
+    int32_t max_depth;         /* stack levels the lowered program needs */
+    int32_t stack_fetches;     /* S operands read from the stack */
+    int32_t n_values;          /* functions plus operands in the lowered form */
+    int32_t n_reversed;        /* instructions whose right operand was evaluated first */
+} gp_lower_stats;
+
+/* Lower one prefix tree (tok/cst HOST, n tokens).  words (HOST, may be NULL)
+ * receives 2 * n_instr uint32 words of device code when non-NULL and
+ * max_words is large enough. */
+gp_status gp_lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat,
+                        uint32_t* words, int64_t max_words, gp_lower_stats* stats);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+/* Kernel timing.  While enabled, every evaluation-kernel launch is bracketed
+ * by two HIP events recorded on its launch stream.  gp_timing_read waits
+ * for the recorded launches, returns how many there were and their summed
+ * duration in milliseconds, and forgets them when reset != 0.  Timing is a
+ * process-wide switch; it is off by default. */
+gp_status gp_timing_enable(int on);
+gp_status gp_timing_read(int64_t* launches, double* total_ms, int reset);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gp_last_error(void);
+/* Library version string. */
+const char* gp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H_ */

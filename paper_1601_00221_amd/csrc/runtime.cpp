@@ -1,0 +1,585 @@
+// Host runtime of the GP population evaluator: argument checks, program
+// lowering and upload, scheduling of (case tile, program group) units, and
+// the C ABI declared in include/gp.h.
+#include <hip/hip_runtime_api.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "gp_internal.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace gpx {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local char t_err[512] = "";
+
+gp_status fail(gp_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_err, sizeof t_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+void clear_error() { t_err[0] = 0; }
+const char* last_error() { return t_err; }
+
+// ---------------------------------------------------------------------------
+// Buffers
+// ---------------------------------------------------------------------------
+gp_status DevBuf::reserve(size_t n) {
+    if (n <= cap) return GP_OK;
+    if (p) {
+        hipError_t e = hipFree(p);  // waits for the device before releasing
+        p = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipFree: %s", hipGetErrorString(e));
+    }
+    size_t want = n < 4096 ? 4096 : n + n / 4;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? GP_E_NOMEM : GP_E_DEVICE, "hipMalloc(%zu): %s", want,
+                    hipGetErrorString(e));
+    }
+    cap = want;
+    return GP_OK;
+}
+
+void DevBuf::release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+gp_status Staging::begin(size_t n) {
+    if (pending) {
+        hipError_t e = hipEventSynchronize(ev);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+        pending = false;
+    }
+    if (!ev) {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    if (n > cap) {
+        if (host) hipHostFree(host);
+        host = nullptr;
+        cap = 0;
+        size_t want = n < 65536 ? 65536 : n + n / 4;
+        hipError_t e = hipHostMalloc(&host, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            host = nullptr;
+            return fail(GP_E_NOMEM, "hipHostMalloc(%zu): %s", want, hipGetErrorString(e));
+        }
+        cap = want;
+    }
+    used = 0;
+    return GP_OK;
+}
+
+gp_status Staging::put(const void* src, size_t n, void* dst, hipStream_t s) {
+    if (n == 0) return GP_OK;
+    memcpy((char*)host + used, src, n);
+    hipError_t e = hipMemcpyAsync(dst, (char*)host + used, n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    used += (n + 255) & ~(size_t)255;
+    return GP_OK;
+}
+
+gp_status Staging::end(hipStream_t s) {
+    hipError_t e = hipEventRecord(ev, s);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    pending = true;
+    return GP_OK;
+}
+
+static std::mutex g_ws_mu;
+static std::unordered_map<hipStream_t, Workspace*> g_ws;
+
+Workspace& workspace(hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto it = g_ws.find(s);
+    if (it != g_ws.end()) return *it->second;
+    Workspace* w = new Workspace();  // lives until process exit
+    g_ws[s] = w;
+    return *w;
+}
+
+// ---------------------------------------------------------------------------
+// Program building
+// ---------------------------------------------------------------------------
+// Relative cost of one instruction, used only to balance program groups.
+static uint32_t op_cost(uint32_t op) {
+    switch (op) {
+        case GP_PDIV: return 12;
+        case GP_SIN: case GP_COS: return 40;
+        case GP_EXPC: case GP_PLOG: return 24;
+        default: return 1;
+    }
+}
+
+gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t P,
+                     int32_t n_feat, ProgData& pd) {
+    if (P < 0) return fail(GP_E_INVAL, "n_prog < 0");
+    if (P > 0 && (!tok || !cst || !off)) return fail(GP_E_INVAL, "null program array");
+    if (n_feat < 1) return fail(GP_E_INVAL, "n_feat < 1");
+    pd = ProgData();
+    pd.form = FORM_TREE;
+    pd.n_prog = P;
+    pd.n_feat = n_feat;
+    if (P == 0) return GP_OK;
+    if (off[0] != 0) return fail(GP_E_INVAL, "off[0] must be 0");
+    int64_t total = 0;
+    for (int32_t p = 0; p < P; p++) {
+        const int64_t n = off[p + 1] - off[p];
+        if (n < 1) return fail(GP_E_INVAL, "program %d is empty", p);
+        if (n > GP_MAX_LEN) return fail(GP_E_DEPTH, "program %d: %lld nodes exceeds %d", p, (long long)n, GP_MAX_LEN);
+        total += n;
+    }
+    pd.code.resize((size_t)total * 2);  // at most one instruction per node
+    pd.progs.resize(P);
+    pd.cost.resize(P);
+    int64_t w = 0;
+    int32_t max_feat = -1;
+    char err[256];
+    for (int32_t p = 0; p < P; p++) {
+        const int64_t n = off[p + 1] - off[p];
+        TreeLowering st;
+        int rc = lower_tree(tok + off[p], cst + off[p], n, n_feat, pd.code.data() + 2 * w, &st, err);
+        if (rc != GP_OK) return fail((gp_status)rc, "program %d: %s", p, err);
+        for (int64_t i = 0; i < n; i++) {
+            const int32_t t = tok[off[p] + i];
+            if ((t & 0xFF) == GP_VAR) max_feat = std::max<int32_t>(max_feat, (int32_t)((uint32_t)t >> 8));
+        }
+        uint32_t cost = 0;
+        for (int32_t i = 0; i < st.n_instr; i++) cost += op_cost(pd.code[2 * (w + i)] & 15u);
+        if (w > 0xFFFFFFFFll - 2 * (int64_t)st.n_instr)
+            return fail(GP_E_INVAL, "programs exceed 2^32 device words");
+        DevProg& d = pd.progs[p];
+        d.code_off = (uint32_t)(2 * w);
+        d.len = (uint32_t)st.n_instr;
+        d.meta = FORM_TREE | ((uint32_t)st.max_depth << 8);
+        d.part_stride = (uint32_t)P;
+        d.part_base = (uint64_t)p;
+        d.row = (uint64_t)p;
+        pd.cost[p] = cost + 8;
+        pd.max_depth = std::max(pd.max_depth, st.max_depth);
+        pd.n_instr += st.n_instr;
+        pd.n_gpop += st.n_nodes;
+        w += st.n_instr;
+    }
+    pd.code.resize((size_t)w * 2);
+    pd.n_load = max_feat + 1 > 0 ? max_feat + 1 : 1;
+    return GP_OK;
+}
+
+gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
+                       int32_t P, int32_t n_reg, int32_t n_feat, ProgData& pd) {
+    if (P < 0) return fail(GP_E_INVAL, "n_prog < 0");
+    if (P > 0 && (!code || !off)) return fail(GP_E_INVAL, "null program array");
+    if (n_reg < 1 || n_reg > GP_MAX_REG) return fail(GP_E_INVAL, "n_reg %d outside [1, %d]", n_reg, GP_MAX_REG);
+    if (n_feat < 1 || n_reg + n_feat > GP_SRC_CONST)
+        return fail(GP_E_INVAL, "n_feat %d: registers plus features must stay below %d", n_feat, GP_SRC_CONST);
+    pd = ProgData();
+    pd.form = FORM_LINEAR;
+    pd.n_prog = P;
+    pd.n_feat = n_feat;
+    pd.n_reg = n_reg;
+    if (P == 0) return GP_OK;
+    if (off[0] != 0) return fail(GP_E_INVAL, "off[0] must be 0");
+    if (cst_off && cst_off[0] != 0) return fail(GP_E_INVAL, "cst_off[0] must be 0");
+    int64_t total = 0;
+    for (int32_t p = 0; p < P; p++) {
+        const int64_t n = off[p + 1] - off[p];
+        const int64_t nc = cst_off ? cst_off[p + 1] - cst_off[p] : 0;
+        if (n < 1) return fail(GP_E_INVAL, "program %d is empty", p);
+        if (n > GP_MAX_LEN) return fail(GP_E_DEPTH, "program %d: %lld instructions exceeds %d", p, (long long)n, GP_MAX_LEN);
+        if (nc < 0 || nc > 256 - GP_SRC_CONST) return fail(GP_E_INVAL, "program %d: %lld constants", p, (long long)nc);
+        if (nc > 0 && !cst) return fail(GP_E_INVAL, "null constant array");
+        total += n + nc;
+    }
+    if (total > 0xFFFFFFFFll) return fail(GP_E_INVAL, "programs exceed 2^32 device words");
+    pd.code.resize((size_t)total);
+    pd.progs.resize(P);
+    pd.cost.resize(P);
+    int64_t w = 0;
+    int32_t max_feat = std::min(n_feat, n_reg) - 1;  // registers start from these features
+    char err[256];
+    for (int32_t p = 0; p < P; p++) {
+        const int64_t n = off[p + 1] - off[p];
+        const int64_t nc = cst_off ? cst_off[p + 1] - cst_off[p] : 0;
+        const uint32_t* src = code + off[p];
+        int rc = check_linear(src, n, nc, n_reg, n_feat, err);
+        if (rc != GP_OK) return fail((gp_status)rc, "program %d: %s", p, err);
+        uint32_t cost = 0;
+        for (int64_t i = 0; i < n; i++) {
+            const uint32_t wd = src[i];
+            const int op = wd & 0xFF;
+            cost += op_cost(op);
+            const int na = op < GP_SIN ? 2 : 1;
+            for (int q = 0; q < na; q++) {
+                const int id = (int)((wd >> (16 + 8 * q)) & 0xFF);
+                if (id >= n_reg && id < GP_SRC_CONST) max_feat = std::max(max_feat, id - n_reg);
+            }
+        }
+        memcpy(pd.code.data() + w, src, sizeof(uint32_t) * (size_t)n);
+        if (nc) memcpy(pd.code.data() + w + n, cst + cst_off[p], sizeof(float) * (size_t)nc);
+        DevProg& d = pd.progs[p];
+        d.code_off = (uint32_t)w;
+        d.len = (uint32_t)n;
+        d.meta = FORM_LINEAR | ((uint32_t)n_reg << 8);
+        d.part_stride = (uint32_t)P;
+        d.part_base = (uint64_t)p;
+        d.row = (uint64_t)p;
+        pd.cost[p] = cost + 8;
+        pd.n_instr += n;
+        pd.n_gpop += n;
+        w += n + nc;
+    }
+    pd.n_load = max_feat + 1;
+    return GP_OK;
+}
+
+// Programs sorted by cost (longest first) and dealt to G groups in snake
+// order, so every group carries about the same work.
+static void make_groups(const ProgData& pd, int32_t G, std::vector<uint32_t>& order,
+                        std::vector<uint32_t>& goff) {
+    const int32_t P = pd.n_prog;
+    std::vector<uint32_t> idx(P);
+    std::iota(idx.begin(), idx.end(), 0u);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return pd.cost[a] > pd.cost[b]; });
+    std::vector<std::vector<uint32_t>> g(G);
+    for (int32_t i = 0; i < P; i++) {
+        const int32_t r = i / G, k = i % G;
+        g[(r & 1) ? G - 1 - k : k].push_back(idx[i]);
+    }
+    order.clear();
+    goff.assign(1, 0);
+    for (int32_t k = 0; k < G; k++) {
+        order.insert(order.end(), g[k].begin(), g[k].end());
+        goff.push_back((uint32_t)order.size());
+    }
+}
+
+gp_status upload_programs(const ProgData& pd, DevProgs& dp, hipStream_t s, Workspace& w) {
+    gp_status st;
+    if ((st = dp.code.reserve(std::max<size_t>(4, pd.code.size() * 4))) != GP_OK) return st;
+    if ((st = dp.progs.reserve(std::max<size_t>(1, pd.progs.size()) * sizeof(DevProg))) != GP_OK) return st;
+    if ((st = w.staging.begin(pd.code.size() * 4 + pd.progs.size() * sizeof(DevProg) + 1024)) != GP_OK) return st;
+    if ((st = w.staging.put(pd.code.data(), pd.code.size() * 4, dp.code.p, s)) != GP_OK) return st;
+    if ((st = w.staging.put(pd.progs.data(), pd.progs.size() * sizeof(DevProg), dp.progs.p, s)) != GP_OK) return st;
+    dp.groups_by_G.clear();
+    return w.staging.end(s);
+}
+
+static gp_status groups_for(const ProgData& pd, DevProgs& dp, int32_t G, hipStream_t s, Workspace& w,
+                            const uint32_t** order, const uint32_t** goff) {
+    auto it = dp.groups_by_G.find(G);
+    if (it == dp.groups_by_G.end()) {
+        std::vector<uint32_t> o, g;
+        make_groups(pd, G, o, g);
+        std::unique_ptr<DevBuf> b(new DevBuf());
+        gp_status st;
+        if ((st = b->reserve((o.size() + g.size()) * 4)) != GP_OK) return st;
+        if ((st = w.staging.begin((o.size() + g.size()) * 4 + 512)) != GP_OK) return st;
+        if ((st = w.staging.put(o.data(), o.size() * 4, b->p, s)) != GP_OK) return st;
+        if ((st = w.staging.put(g.data(), g.size() * 4, (uint32_t*)b->p + o.size(), s)) != GP_OK) return st;
+        if ((st = w.staging.end(s)) != GP_OK) return st;
+        it = dp.groups_by_G.emplace(G, std::make_pair((int64_t)o.size(), std::move(b))).first;
+    }
+    *order = (const uint32_t*)it->second.second->p;
+    *goff = *order + it->second.first;
+    return GP_OK;
+}
+
+// Number of program groups: enough (tile, group) units to keep every
+// wavefront slot of the chip busy several times over.
+static int32_t choose_groups(int32_t P, int32_t tiles, int32_t target_units) {
+    int64_t g = (target_units + (int64_t)tiles - 1) / tiles;
+    if (g < 1) g = 1;
+    if (g > P) g = P;
+    return (int32_t)g;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------------
+static std::mutex g_tm_mu;
+static bool g_tm_on = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tm_events;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tm_free;
+
+hipError_t timed_launch_begin(hipStream_t s, int* slot) {
+    *slot = -1;
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    if (!g_tm_on) return hipSuccess;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!g_tm_free.empty()) {
+        ev = g_tm_free.back();
+        g_tm_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev.first);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(ev.first, s);
+    if (e != hipSuccess) return e;
+    g_tm_events.push_back(ev);
+    *slot = (int)g_tm_events.size() - 1;
+    return hipSuccess;
+}
+
+hipError_t timed_launch_end(hipStream_t s, int slot) {
+    if (slot < 0) return hipSuccess;
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    return hipEventRecord(g_tm_events[slot].second, s);
+}
+
+gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_feat, int64_t N,
+                    const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
+                    const EvalOptions* opt) {
+    if (!X) return fail(GP_E_INVAL, "X is null");
+    if (!out) return fail(GP_E_INVAL, "out is null");
+    if (N < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
+    if (kind < GP_FIT_SUM_ABS || kind > GP_OUT_CASES) return fail(GP_E_INVAL, "unknown fitness kind %d", kind);
+    if (kind != GP_OUT_CASES && !y) return fail(GP_E_INVAL, "y is null");
+    if (n_feat < pd.n_feat) return fail(GP_E_INVAL, "case matrix has %d features, programs need %d", n_feat, pd.n_feat);
+    if (pd.n_prog == 0) return GP_OK;
+    if (pd.n_load > GP_MAX_FEAT)
+        return fail(GP_E_INVAL, "programs read feature %d; at most %d features are supported", pd.n_load - 1, GP_MAX_FEAT);
+    int vi = opt && opt->variant >= 0 ? opt->variant : pick_variant(pd.n_load, pd.max_depth);
+    if (vi < 0 || vi >= n_variants()) return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
+    const VariantDesc& v = variant(vi);
+    if (v.fv < pd.n_load || v.d < pd.max_depth) return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
+    const int64_t tiles64 = (N + 64LL * v.t - 1) / (64LL * v.t);
+    if (tiles64 > (1LL << 30)) return fail(GP_E_INVAL, "n_cases too large");
+    const int32_t tiles = (int32_t)tiles64;
+    const int32_t target = opt && opt->target_units > 0 ? opt->target_units : 16384;
+    const int32_t G = opt && opt->groups > 0 ? std::min(opt->groups, pd.n_prog) : choose_groups(pd.n_prog, tiles, target);
+    const int64_t units = (int64_t)tiles * G;
+    if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
+    gp_status st;
+    const uint32_t *order, *goff;
+    if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
+    if (kind != GP_OUT_CASES) {
+        if ((st = w.partials.reserve((size_t)tiles * pd.n_prog * sizeof(double))) != GP_OK) return st;
+    }
+    EvalArgs a;
+    memset(&a, 0, sizeof a);
+    a.code = (const uint32_t*)dp.code.p;
+    a.progs = (const DevProg*)dp.progs.p;
+    a.order = order;
+    a.group_off = goff;
+    a.X = X;
+    a.y = kind == GP_OUT_CASES ? nullptr : y;
+    a.partials = (double*)w.partials.p;
+    a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
+    a.N = N;
+    a.n_load = pd.n_load;
+    a.n_feat_prog = pd.n_feat;
+    a.tiles = tiles;
+    a.n_units = (int32_t)units;
+    a.kind = kind;
+    int slot;
+    hipError_t e = timed_launch_begin(s, &slot);
+    if (e == hipSuccess) e = launch_eval(vi, a, s);
+    if (e == hipSuccess) e = timed_launch_end(s, slot);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "evaluation launch: %s", hipGetErrorString(e));
+    if (kind == GP_OUT_CASES) return GP_OK;
+    ReduceArgs r;
+    memset(&r, 0, sizeof r);
+    r.partials = (const double*)w.partials.p;
+    r.part_base = 0;
+    r.stride = pd.n_prog;
+    r.n_prog = pd.n_prog;
+    r.N = N;
+    r.out = out;
+    r.tiles = tiles;
+    r.kind = kind;
+    e = launch_reduce(r, s);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "reduction launch: %s", hipGetErrorString(e));
+    return GP_OK;
+}
+
+}  // namespace gpx
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace gpx;
+
+struct gp_progset {
+    ProgData pd;
+    DevProgs dp;
+    std::mutex mu;
+};
+
+extern "C" {
+
+const char* gp_last_error(void) { return last_error(); }
+
+const char* gp_version(void) { return "gp2d 0.1 (gfx950)"; }
+
+gp_status gp_eval_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog,
+                       const float* X, int32_t n_feat, int64_t n_cases, const float* y, int32_t kind,
+                       void* out, void* stream) {
+    clear_error();
+    ProgData pd;
+    gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd);
+    if (st != GP_OK || n_prog == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& w = workspace(s);
+    std::lock_guard<std::mutex> g(w.mu);
+    if ((st = upload_programs(pd, w.oneshot, s, w)) != GP_OK) return st;
+    return eval_core(pd, w.oneshot, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+}
+
+gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
+                         int32_t n_prog, int32_t n_reg, const float* X, int32_t n_feat, int64_t n_cases,
+                         const float* y, int32_t kind, void* out, void* stream) {
+    clear_error();
+    ProgData pd;
+    gp_status st = build_linear(code, off, cst, cst_off, n_prog, n_reg, n_feat, pd);
+    if (st != GP_OK || n_prog == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& w = workspace(s);
+    std::lock_guard<std::mutex> g(w.mu);
+    if ((st = upload_programs(pd, w.oneshot, s, w)) != GP_OK) return st;
+    return eval_core(pd, w.oneshot, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+}
+
+static gp_status progset_finish(ProgData&& pd, void* stream, gp_progset** ps) {
+    std::unique_ptr<gp_progset> p(new gp_progset());
+    p->pd = std::move(pd);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->pd.n_prog > 0) {
+        Workspace& w = workspace(s);
+        std::lock_guard<std::mutex> g(w.mu);
+        gp_status st = upload_programs(p->pd, p->dp, s, w);
+        if (st != GP_OK) return st;
+    }
+    *ps = p.release();
+    return GP_OK;
+}
+
+gp_status gp_progset_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog,
+                          int32_t n_feat, void* stream, gp_progset** ps) {
+    clear_error();
+    if (!ps) return fail(GP_E_INVAL, "ps is null");
+    ProgData pd;
+    gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd);
+    if (st != GP_OK) return st;
+    return progset_finish(std::move(pd), stream, ps);
+}
+
+gp_status gp_progset_linear(const uint32_t* code, const int64_t* off, const float* cst,
+                            const int64_t* cst_off, int32_t n_prog, int32_t n_reg, int32_t n_feat,
+                            void* stream, gp_progset** ps) {
+    clear_error();
+    if (!ps) return fail(GP_E_INVAL, "ps is null");
+    ProgData pd;
+    gp_status st = build_linear(code, off, cst, cst_off, n_prog, n_reg, n_feat, pd);
+    if (st != GP_OK) return st;
+    return progset_finish(std::move(pd), stream, ps);
+}
+
+gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                          int32_t kind, void* out, void* stream) {
+    clear_error();
+    if (!ps) return fail(GP_E_INVAL, "ps is null");
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& w = workspace(s);
+    std::lock_guard<std::mutex> g(w.mu);
+    std::lock_guard<std::mutex> g2(ps->mu);
+    return eval_core(ps->pd, ps->dp, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+}
+
+gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
+    clear_error();
+    if (!ps || !info) return fail(GP_E_INVAL, "null argument");
+    info->n_prog = ps->pd.n_prog;
+    info->form = ps->pd.form;
+    info->n_feat = ps->pd.n_feat;
+    info->max_depth = ps->pd.max_depth;
+    info->n_instr = ps->pd.n_instr;
+    info->n_gpop = ps->pd.n_gpop;
+    return GP_OK;
+}
+
+gp_status gp_progset_destroy(gp_progset* ps) {
+    clear_error();
+    if (!ps) return GP_OK;
+    ps->dp.release();
+    delete ps;
+    return GP_OK;
+}
+
+gp_status gp_timing_enable(int on) {
+    clear_error();
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    g_tm_on = on != 0;
+    return GP_OK;
+}
+
+gp_status gp_timing_read(int64_t* launches, double* total_ms, int reset) {
+    clear_error();
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    double ms = 0.0;
+    for (auto& ev : g_tm_events) {
+        hipError_t e = hipEventSynchronize(ev.second);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, ev.first, ev.second);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventElapsedTime: %s", hipGetErrorString(e));
+        ms += t;
+    }
+    if (launches) *launches = (int64_t)g_tm_events.size();
+    if (total_ms) *total_ms = ms;
+    if (reset) {
+        g_tm_free.insert(g_tm_free.end(), g_tm_events.begin(), g_tm_events.end());
+        g_tm_events.clear();
+    }
+    return GP_OK;
+}
+
+gp_status gp_lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, uint32_t* words,
+                        int64_t max_words, gp_lower_stats* stats) {
+    clear_error();
+    if (!tok || !cst) return fail(GP_E_INVAL, "null program");
+    if (n_feat < 1) return fail(GP_E_INVAL, "n_feat < 1");
+    if (n > GP_MAX_LEN) return fail(GP_E_DEPTH, "program of %lld nodes exceeds %d", (long long)n, GP_MAX_LEN);
+    std::vector<uint32_t> buf(2 * (size_t)std::max<int64_t>(n, 1));
+    TreeLowering st;
+    char err[256];
+    int rc = lower_tree(tok, cst, n, n_feat, buf.data(), &st, err);
+    if (rc != GP_OK) return fail((gp_status)rc, "%s", err);
+    if (words) {
+        if (max_words < 2 * (int64_t)st.n_instr) return fail(GP_E_INVAL, "words buffer too small");
+        memcpy(words, buf.data(), sizeof(uint32_t) * 2 * (size_t)st.n_instr);
+    }
+    if (stats) {
+        stats->n_nodes = st.n_nodes;
+        stats->n_instr = st.n_instr;
+        stats->max_depth = st.max_depth;
+        stats->stack_fetches = st.stack_fetches;
+        stats->n_values = st.n_values;
+        stats->n_reversed = st.n_reversed;
+    }
+    return GP_OK;
+}
+
+}  // extern "C"

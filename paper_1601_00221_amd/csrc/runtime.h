@@ -1,0 +1,96 @@
+// Host runtime internals shared by the evaluation, batching and serving code.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "gp_internal.h"
+
+namespace gpx {
+
+gp_status fail(gp_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+const char* last_error();
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    gp_status reserve(size_t n);
+    void release();
+};
+
+// Pinned host staging for host-to-device copies.  begin() waits until the
+// copies of the previous use have left the buffer.
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    gp_status begin(size_t n);
+    gp_status put(const void* src, size_t n, void* dst, hipStream_t s);
+    gp_status end(hipStream_t s);
+};
+
+// Lowered programs on the host.
+struct ProgData {
+    int form = 0;
+    int32_t n_prog = 0;
+    int32_t n_feat = 0;     // declared feature count (register initialisation wraps around it)
+    int32_t n_reg = 0;
+    int32_t n_load = 1;     // features the programs actually read (max index + 1)
+    int32_t max_depth = 0;
+    int64_t n_instr = 0;
+    int64_t n_gpop = 0;     // GP operations per case: tree nodes or linear instructions
+    std::vector<uint32_t> code;
+    std::vector<DevProg> progs;
+    std::vector<uint32_t> cost;
+};
+
+// Device copies of lowered programs plus cached group layouts.
+struct DevProgs {
+    DevBuf code;
+    DevBuf progs;
+    std::map<int32_t, std::pair<int64_t, std::unique_ptr<DevBuf>>> groups_by_G;
+    void release() {
+        code.release();
+        progs.release();
+        for (auto& kv : groups_by_G) kv.second.second->release();
+        groups_by_G.clear();
+    }
+};
+
+// Per-stream scratch: partial sums, staging and the one-shot program buffers.
+struct Workspace {
+    std::mutex mu;
+    DevBuf partials;
+    Staging staging;
+    DevProgs oneshot;
+};
+
+struct EvalOptions {
+    int variant = -1;        // kernel variant index, -1 = pick by footprint
+    int32_t groups = 0;      // program groups, 0 = automatic
+    int32_t target_units = 0;
+};
+
+Workspace& workspace(hipStream_t s);
+
+gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t P, int32_t n_feat,
+                     ProgData& pd);
+gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
+                       int32_t P, int32_t n_reg, int32_t n_feat, ProgData& pd);
+gp_status upload_programs(const ProgData& pd, DevProgs& dp, hipStream_t s, Workspace& w);
+gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_feat, int64_t N, const float* y,
+                    int32_t kind, void* out, hipStream_t s, Workspace& w, const EvalOptions* opt);
+
+}  // namespace gpx
