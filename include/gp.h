@@ -141,6 +141,123 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info);
 gp_status gp_progset_destroy(gp_progset* ps);
 
 /* ------------------------------------------------------------------------ */
+/* Batched evaluation: several populations (trees and linear programs) over */
+/* several resident case matrices in one persistent launch.  Work is cut   */
+/* into (case tile, program group) units, sorted longest first and pulled  */
+/* by the chip's resident wavefronts from a global counter.  Fitness values */
+/* are the same as from gp_eval_tree / gp_eval_linear, bit for bit.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const float* X;            /* DEVICE, feature-major float32[n_feat * n_cases] */
+    int32_t n_feat;
+    int64_t n_cases;
+    const float* y;            /* DEVICE, float32[n_cases] */
+} gp_dataset;
+
+enum { GP_FORM_TREE = 0, GP_FORM_LINEAR = 1 };
+
+typedef struct {
+    int32_t form;              /* GP_FORM_TREE or GP_FORM_LINEAR */
+    int32_t n_prog;
+    int32_t dataset;           /* index into the dataset array */
+    int32_t kind;              /* GP_FIT_SUM_ABS, GP_FIT_MSE or GP_FIT_HITS */
+    /* trees (HOST, as in gp_eval_tree) */
+    const int32_t* tok;
+    const float* tcst;
+    const int64_t* toff;
+    /* linear programs (HOST, as in gp_eval_linear) */
+    const uint32_t* code;
+    const int64_t* loff;
+    const float* lcst;
+    const int64_t* lcst_off;
+    int32_t n_reg;
+    void* out;                 /* DEVICE: float[n_prog] or int32[n_prog] (hits) */
+} gp_job;
+
+typedef struct {
+    int32_t variant;           /* kernel variant (tile width, stack depth, feature slots) */
+    int32_t unit_programs;     /* programs per work unit */
+    int32_t persistent;        /* 1: resident waves pull units longest first; 0: one wave per unit */
+    int32_t reserved;
+} gp_batch_config;
+
+/* cfg NULL: the configuration the autotuner stored for this batch shape,
+ * else a default.  Stream ordered and asynchronous like gp_eval_tree. */
+gp_status gp_eval_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, int32_t n_jobs,
+                        const gp_batch_config* cfg, void* stream);
+/* Time every candidate configuration `reps` times on this batch (runs on
+ * `stream` and synchronizes on it), store the fastest for the batch's shape
+ * and return it with its median time.  The store is kept in memory and, when
+ * the environment names a file in GP2D_TUNE_CACHE, in that JSON file. */
+gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, int32_t n_jobs, int32_t reps,
+                        gp_batch_config* best, double* best_ms, void* stream);
+/* Compiled kernel variants: tile width t (case slots per lane), stack levels
+ * and feature slots. */
+int32_t gp_num_variants(void);
+gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: concurrent GP runs submit population evaluations against        */
+/* datasets resident in device memory.  A scheduler thread admits requests  */
+/* while their device memory fits the budget (FIFO), fuses the admitted     */
+/* ones into one batched launch and keeps up to n_streams launches in       */
+/* flight, so requests arriving while the GPU is busy start as soon as a    */
+/* stream frees up (continuous batching).  A request's fitness values are   */
+/* bit-identical to evaluating it alone.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct gp_server gp_server;
+
+typedef struct {
+    size_t memory_budget;      /* device bytes admitted work may hold (lowered programs, unit
+                                  tables, partial sums); 0 = 4 GiB */
+    int32_t max_queue;         /* requests waiting for admission; beyond it submit returns
+                                  GP_E_AGAIN; 0 = 1024 */
+    int32_t n_streams;         /* batched launches in flight at once; 0 = 2, at most 8 */
+    int32_t max_batch;         /* requests fused into one launch; 0 = 64 */
+    int32_t batching;          /* 0: one launch per request on one stream (the comparison
+                                  baseline); nonzero: continuous batching */
+    int32_t dry_run;           /* nonzero: schedule without a device -- nothing is launched and
+                                  outputs are not written; a batch "runs" for its GP operation
+                                  count divided by dry_run_gpops seconds (for testing the
+                                  scheduler) */
+    double dry_run_gpops;
+} gp_serve_config;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, cancelled, failed;
+    int32_t queue_depth;       /* requests waiting for admission */
+    int32_t in_flight_batches;
+    int64_t bytes_in_flight;   /* admitted, unfinished requests */
+    int64_t batches;
+    double mean_batch;         /* requests per launch */
+    double p50_us, p99_us;     /* submit-to-completion latency over recent requests */
+    double gpops_per_s;        /* GP operations completed / (last completion - first submit) */
+} gp_serve_stats_t;
+
+gp_status gp_serve_create(const gp_serve_config* cfg, gp_server** s);
+/* Register a resident dataset (DEVICE pointers, kept alive by the caller
+ * until gp_serve_destroy); *id is its index for requests. */
+gp_status gp_serve_add_dataset(gp_server* s, const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                               int32_t* id);
+/* Validate and lower the request's programs on the calling thread, then
+ * queue it.  req->dataset is a dataset id.  GP_E_NOMEM if it can never fit
+ * the budget, GP_E_AGAIN if the queue is full, GP_E_NOTFOUND for an unknown
+ * dataset.  Programs are copied; req->out must stay valid until done. */
+gp_status gp_serve_submit(gp_server* s, const gp_job* req, uint64_t* ticket);
+/* *done = 1 once the request finished (returns its failure status if it failed). */
+gp_status gp_serve_poll(gp_server* s, uint64_t ticket, int32_t* done);
+/* Wait for completion; timeout_us < 0 waits forever.  GP_E_TIMEOUT if it
+ * did not finish in time. */
+gp_status gp_serve_wait(gp_server* s, uint64_t ticket, int64_t timeout_us);
+/* Cancel a request that has not been admitted yet (GP_E_AGAIN otherwise). */
+gp_status gp_serve_cancel(gp_server* s, uint64_t ticket);
+/* Forget a finished ticket. */
+gp_status gp_serve_release(gp_server* s, uint64_t ticket);
+gp_status gp_serve_stats(gp_server* s, gp_serve_stats_t* out);
+/* Cancel queued requests, wait for launched ones, free everything. */
+gp_status gp_serve_destroy(gp_server* s);
+
+/* ------------------------------------------------------------------------ */
 /* Host-side lowering, exposed for inspection and tests (no GPU needed).    */
 /* ------------------------------------------------------------------------ */
 typedef struct {

@@ -64,11 +64,24 @@ def lib():
             "gp_lower_tree": [P, P, i64, i32, P, i64, P],
             "gp_timing_enable": [C.c_int],
             "gp_timing_read": [P, P, C.c_int],
+            "gp_eval_batch": [P, i32, P, i32, P, P],
+            "gp_tune_batch": [P, i32, P, i32, i32, P, P, P],
+            "gp_variant_info": [i32, P, P, P],
+            "gp_serve_create": [P, P],
+            "gp_serve_add_dataset": [P, P, i32, i64, P, P],
+            "gp_serve_submit": [P, P, P],
+            "gp_serve_poll": [P, C.c_uint64, P],
+            "gp_serve_wait": [P, C.c_uint64, i64],
+            "gp_serve_cancel": [P, C.c_uint64],
+            "gp_serve_release": [P, C.c_uint64],
+            "gp_serve_stats": [P, P],
+            "gp_serve_destroy": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
+        L.gp_num_variants.restype = C.c_int32
         L.gp_last_error.restype = C.c_char_p
         L.gp_version.restype = C.c_char_p
         _lib = L
@@ -216,6 +229,172 @@ def timing_read(reset: bool = True):
     ms = C.c_double()
     check(lib().gp_timing_read(C.byref(n), C.byref(ms), 1 if reset else 0))
     return n.value, ms.value
+
+
+# ---------------------------------------------------------------------------
+# Batched evaluation and serving
+# ---------------------------------------------------------------------------
+class Dataset(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("n_feat", C.c_int32), ("n_cases", C.c_int64), ("y", C.c_void_p)]
+
+
+class Job(C.Structure):
+    _fields_ = [("form", C.c_int32), ("n_prog", C.c_int32), ("dataset", C.c_int32), ("kind", C.c_int32),
+                ("tok", C.c_void_p), ("tcst", C.c_void_p), ("toff", C.c_void_p),
+                ("code", C.c_void_p), ("loff", C.c_void_p), ("lcst", C.c_void_p), ("lcst_off", C.c_void_p),
+                ("n_reg", C.c_int32), ("out", C.c_void_p)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("unit_programs", C.c_int32), ("persistent", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {"variant": self.variant, "unit_programs": self.unit_programs, "persistent": self.persistent}
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("memory_budget", C.c_size_t), ("max_queue", C.c_int32), ("n_streams", C.c_int32),
+                ("max_batch", C.c_int32), ("batching", C.c_int32), ("dry_run", C.c_int32),
+                ("dry_run_gpops", C.c_double)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("cancelled", C.c_int64), ("failed", C.c_int64),
+                ("queue_depth", C.c_int32), ("in_flight_batches", C.c_int32), ("bytes_in_flight", C.c_int64),
+                ("batches", C.c_int64), ("mean_batch", C.c_double), ("p50_us", C.c_double),
+                ("p99_us", C.c_double), ("gpops_per_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def make_job(pop, dataset, kind, out):
+    """A gp_job for a synth.TreePop / synth.LinearPop (host arrays are kept
+    alive on the returned object)."""
+    j = Job()
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    j.n_prog = pop.n_prog
+    j.dataset = dataset
+    j.kind = kind_id(kind)
+    if hasattr(pop, "tok"):
+        j.form = 0
+        j.tok, j.tcst, j.toff = arr(pop.tok, np.int32), arr(pop.cst, np.float32), arr(pop.off, np.int64)
+    else:
+        j.form = 1
+        j.code, j.loff = arr(pop.code, np.uint32), arr(pop.off, np.int64)
+        j.lcst, j.lcst_off = arr(pop.cst, np.float32), arr(pop.cst_off, np.int64)
+        j.n_reg = pop.n_reg
+    j.out = dptr(out).value if out is not None else None
+    j._keep = keep
+    return j
+
+
+def _datasets(ds):
+    arr = (Dataset * len(ds))()
+    for i, (X, y) in enumerate(ds):
+        arr[i].X = X.data_ptr()
+        arr[i].n_feat = int(X.shape[0])
+        arr[i].n_cases = int(X.shape[1])
+        arr[i].y = y.data_ptr() if y is not None else None
+    return arr
+
+
+def gp_eval_batch(datasets, jobs, config=None, stream=None):
+    """datasets: list of (X, y) device tensors; jobs: list of Job (make_job)."""
+    ds = _datasets(datasets)
+    ja = (Job * len(jobs))(*jobs)
+    cfg = C.byref(config) if config is not None else None
+    check(lib().gp_eval_batch(ds, len(datasets), ja, len(jobs), cfg, stream_ptr(stream)))
+
+
+def gp_tune_batch(datasets, jobs, reps=3, stream=None):
+    ds = _datasets(datasets)
+    ja = (Job * len(jobs))(*jobs)
+    best = BatchConfig()
+    ms = C.c_double()
+    check(lib().gp_tune_batch(ds, len(datasets), ja, len(jobs), reps, C.byref(best), C.byref(ms),
+                              stream_ptr(stream)))
+    return best, ms.value
+
+
+def variants():
+    L = lib()
+    out = []
+    for i in range(L.gp_num_variants()):
+        t, d, f = C.c_int32(), C.c_int32(), C.c_int32()
+        check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f)))
+        out.append({"t": t.value, "depth": d.value, "n_feat": f.value})
+    return out
+
+
+class Server:
+    """gp_serve_*: continuous-batching evaluation server."""
+
+    def __init__(self, memory_budget=0, max_queue=0, n_streams=0, max_batch=0, batching=True,
+                 dry_run=False, dry_run_gpops=0.0):
+        cfg = ServeConfig(memory_budget, max_queue, n_streams, max_batch, 1 if batching else 0,
+                          1 if dry_run else 0, dry_run_gpops)
+        self._h = C.c_void_p()
+        check(lib().gp_serve_create(C.byref(cfg), C.byref(self._h)))
+        self._jobs = {}
+
+    def add_dataset(self, X, y, n_feat=None, n_cases=None):
+        i = C.c_int32()
+        if isinstance(X, int):
+            check(lib().gp_serve_add_dataset(self._h, C.c_void_p(X), n_feat, n_cases, C.c_void_p(y), C.byref(i)))
+        else:
+            check(lib().gp_serve_add_dataset(self._h, dptr(X), int(X.shape[0]), int(X.shape[1]), dptr(y),
+                                             C.byref(i)))
+        return i.value
+
+    def submit(self, job):
+        t = C.c_uint64()
+        check(lib().gp_serve_submit(self._h, C.byref(job), C.byref(t)))
+        return t.value
+
+    def try_submit(self, job):
+        """Returns (status, ticket) instead of raising."""
+        t = C.c_uint64()
+        rc = lib().gp_serve_submit(self._h, C.byref(job), C.byref(t))
+        return rc, t.value
+
+    def poll(self, ticket):
+        d = C.c_int32()
+        check(lib().gp_serve_poll(self._h, ticket, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket, timeout_us=-1):
+        return lib().gp_serve_wait(self._h, ticket, timeout_us)
+
+    def cancel(self, ticket):
+        return lib().gp_serve_cancel(self._h, ticket)
+
+    def release(self, ticket):
+        return lib().gp_serve_release(self._h, ticket)
+
+    def stats(self):
+        st = ServeStats()
+        check(lib().gp_serve_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            check(lib().gp_serve_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def out_tensor(kind, n_prog, n_cases, device="cuda"):

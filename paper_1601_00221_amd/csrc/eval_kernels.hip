@@ -245,7 +245,14 @@ __device__ __forceinline__ vec_t<T> run_linear(const uint32_t* __restrict__ code
 }
 
 // --------------------------------------------------------------------------
-// Evaluation kernel: one wavefront per unit (tile, program group).
+// One unit of work: a wave's case tile and a range of programs.
+//
+// Partial sums are formed per block of 256 consecutive cases (4 slots of
+// every lane): each lane adds its 4 terms in slot order, the wave adds the
+// 64 lane sums with a fixed butterfly, and block b of program p is stored at
+// part_base + b * part_stride.  The same blocks arise for any tile width, so
+// a program's fitness does not depend on the kernel variant, on how programs
+// were grouped, or on what else shared the launch.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -253,21 +260,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int T, int D, int FV>
-__global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // Blocks go to the 8 XCDs round robin; give each XCD a contiguous range
-    // of units so a program group's code stays in one L2.
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t lb = (b & 7u) * (nb >> 3) + (b >> 3);
-    const uint32_t u = lb * 4u + wib;
-    if (u >= (uint32_t)a.n_units) return;
-    const uint32_t tile = u % (uint32_t)a.tiles;
-    const uint32_t grp = u / (uint32_t)a.tiles;
+struct UnitCtx {
+    const uint32_t* code;
+    const DevProg* progs;
+    const uint32_t* order;
+    const float* X;
+    const float* y;
+    double* partials;
+    float* cases_out;
+    int64_t N;
+    int32_t n_load;
+    int32_t n_feat_prog;
+    int32_t kind;
+};
 
+template <int T, int D, int FV>
+__device__ __forceinline__ void process_unit(const UnitCtx& a, uint32_t tile, uint32_t q0, uint32_t q1) {
+    static_assert(T % 4 == 0, "a tile holds whole 256-case blocks");
+    const uint32_t lane = threadIdx.x & 63u;
     const int64_t N = a.N;
     const int64_t base = (int64_t)tile * (64 * T) + lane;
+    const int64_t n_blocks = (N + 255) / 256;
     ivec_t<FV> fx[T];
     vec_t<T> yv;
     bool valid[T];
@@ -281,7 +294,6 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
         yv[j] = (a.y != nullptr && valid[j]) ? a.y[c] : 0.0f;
     }
 
-    const uint32_t q0 = a.group_off[grp], q1 = a.group_off[grp + 1];
     for (uint32_t q = q0; q < q1; ++q) {
         const DevProg P = a.progs[a.order[q]];
         vec_t<T> o;
@@ -296,38 +308,104 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
 #pragma unroll
             for (int j = 0; j < T; j++)
                 if (valid[j]) row[base + 64 * j] = o[j];
-        } else if (a.kind == GP_FIT_HITS) {
-            uint32_t hits = 0;
+            continue;
+        }
 #pragma unroll
-            for (int j = 0; j < T; j++) {
-                const bool hit = valid[j] && ((o[j] > 0.0f) == (yv[j] > 0.0f));
-                hits += (uint32_t)__popcll(__ballot(hit));
-            }
-            if (lane == 0) a.partials[P.part_base + (uint64_t)tile * P.part_stride] = (double)hits;
-        } else {
-            double acc = 0.0;
+        for (int k = 0; k < T / 4; k++) {
+            const int64_t blk = (int64_t)tile * (T / 4) + k;
+            double v;
+            if (a.kind == GP_FIT_HITS) {
+                uint32_t hits = 0;
 #pragma unroll
-            for (int j = 0; j < T; j++) {
-                const float d = o[j] - yv[j];
-                const float t = (a.kind == GP_FIT_MSE) ? d * d : fabsf(d);
-                acc += valid[j] ? (double)t : 0.0;
+                for (int j = 4 * k; j < 4 * k + 4; j++) {
+                    const bool hit = valid[j] && ((o[j] > 0.0f) == (yv[j] > 0.0f));
+                    hits += (uint32_t)__popcll(__ballot(hit));
+                }
+                v = (double)hits;
+            } else {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 4 * k; j < 4 * k + 4; j++) {
+                    const float d = o[j] - yv[j];
+                    const float t = (a.kind == GP_FIT_MSE) ? d * d : fabsf(d);
+                    acc += valid[j] ? (double)t : 0.0;
+                }
+                v = wave_sum(acc);
             }
-            acc = wave_sum(acc);
-            if (lane == 0) a.partials[P.part_base + (uint64_t)tile * P.part_stride] = acc;
+            if (lane == 0 && blk < n_blocks) a.partials[P.part_base + (uint64_t)blk * P.part_stride] = v;
         }
     }
 }
 
-// Fixed-order reduction over tiles: thread p sums partial[t*P + p], t = 0..tiles-1.
+// Plain evaluation: unit u = (tile, group) with tile = u mod tiles.
+template <int T, int D, int FV>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Blocks go to the 8 XCDs round robin; give each XCD a contiguous range
+    // of units so a program group's code stays in one L2.
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t lb = (b & 7u) * (nb >> 3) + (b >> 3);
+    const uint32_t u = lb * 4u + wib;
+    if (u >= (uint32_t)a.n_units) return;
+    const uint32_t tile = u % (uint32_t)a.tiles;
+    const uint32_t grp = u / (uint32_t)a.tiles;
+    UnitCtx c{a.code, a.progs, a.order, a.X, a.y, a.partials, a.cases_out, a.N, a.n_load, a.n_feat_prog, a.kind};
+    process_unit<T, D, FV>(c, tile, a.group_off[grp], a.group_off[grp + 1]);
+}
+
+// Batched evaluation over several jobs and datasets.  Persistent form: each
+// wave takes the next unit from a global counter until none is left (units
+// are sorted longest first on the host).  Static form: one wave per unit.
+template <int T, int D, int FV>
+__global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t u = 0;
+    if (!a.persistent) {
+        const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        u = blockIdx.x * 4u + wib;
+    }
+    for (;;) {
+        if (a.persistent) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(a.counter, 1u);
+            u = __builtin_amdgcn_readfirstlane(t);
+        }
+        if (u >= (uint32_t)a.n_units) return;
+        const UnitDesc ud = a.units[u];
+        const JobDesc jd = a.jobs[ud.job];
+        const DatasetDesc dd = a.datasets[jd.ds];
+        UnitCtx c{a.code, a.progs, a.order, dd.X, dd.y, a.partials, nullptr, dd.N, jd.n_load, jd.n_feat_prog,
+                  jd.kind};
+        process_unit<T, D, FV>(c, ud.tile, ud.q0, ud.q1);
+        if (!a.persistent) return;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
+// Fixed-order reduction over blocks: program p of job j sums
+// partial[base_j + b * P_j + p] for b = 0 .. blocks_j - 1.
+__device__ __forceinline__ void reduce_one(const double* partials, uint64_t part_base, int64_t stride, int64_t p,
+                                           int64_t N, int32_t blocks, int32_t kind, void* out) {
+    const double* src = partials + part_base + p;
+    double s = 0.0;
+    for (int32_t t = 0; t < blocks; t++) s += src[(int64_t)t * stride];
+    if (kind == GP_FIT_HITS) ((int32_t*)out)[p] = (int32_t)s;
+    else if (kind == GP_FIT_MSE) ((float*)out)[p] = (float)(s / (double)N);
+    else ((float*)out)[p] = (float)s;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs r) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= r.n_prog) return;
-    const double* src = r.partials + r.part_base + p;
-    double s = 0.0;
-    for (int32_t t = 0; t < r.tiles; t++) s += src[(int64_t)t * r.stride];
-    if (r.kind == GP_FIT_HITS) ((int32_t*)r.out)[p] = (int32_t)s;
-    else if (r.kind == GP_FIT_MSE) ((float*)r.out)[p] = (float)(s / (double)r.N);
-    else ((float*)r.out)[p] = (float)s;
+    reduce_one(r.partials, r.part_base, r.stride, p, r.N, r.blocks, r.kind, r.out);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_jobs(const ReduceArgs* jobs) {
+    const ReduceArgs r = jobs[blockIdx.y];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= r.n_prog) return;
+    reduce_one(r.partials, r.part_base, r.stride, p, r.N, r.blocks, r.kind, r.out);
 }
 
 // --------------------------------------------------------------------------
@@ -352,7 +430,6 @@ int n_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const VariantDesc& variant(int i) { return kVariants[i]; }
 
 int pick_variant(int n_feat_load, int depth) {
-    // smallest register footprint that fits
     int best = -1;
     for (int i = 0; i < n_variants(); i++) {
         const VariantDesc& v = kVariants[i];
@@ -360,7 +437,7 @@ int pick_variant(int n_feat_load, int depth) {
         if (best < 0) { best = i; continue; }
         const VariantDesc& b = kVariants[best];
         const int cost_v = v.t * (v.d + v.fv), cost_b = b.t * (b.d + b.fv);
-        // prefer the wider tile when the register footprint allows it
+        // prefer the wider tile, then the smaller register footprint
         if (v.t > b.t || (v.t == b.t && cost_v < cost_b)) best = i;
     }
     return best;
@@ -371,20 +448,59 @@ hipError_t launch_eval(int vi, const EvalArgs& a, hipStream_t s) {
     uint32_t blocks = (uint32_t)((a.n_units + 3) / 4);
     blocks = (blocks + 7u) & ~7u;
     const VariantDesc& v = kVariants[vi];
-#define GPX_LAUNCH(T, D, FV)                                                   \
-    if (v.t == T && v.d == D && v.fv == FV) {                                  \
+#define GPX_LAUNCH(T, D, FV)                                                      \
+    if (v.t == T && v.d == D && v.fv == FV) {                                     \
         hipLaunchKernelGGL((k_eval<T, D, FV>), dim3(blocks), dim3(256), 0, s, a); \
-        return hipGetLastError();                                              \
+        return hipGetLastError();                                                 \
     }
     GPX_VARIANTS(GPX_LAUNCH)
 #undef GPX_LAUNCH
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_batch(int vi, const BatchArgs& a, uint32_t grid_blocks, hipStream_t s) {
+    if (a.n_units <= 0) return hipSuccess;
+    if (a.persistent) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.counter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else {
+        grid_blocks = (uint32_t)((a.n_units + 3) / 4);
+    }
+    const VariantDesc& v = kVariants[vi];
+#define GPX_LAUNCH(T, D, FV)                                                                \
+    if (v.t == T && v.d == D && v.fv == FV) {                                               \
+        hipLaunchKernelGGL((k_batch<T, D, FV>), dim3(grid_blocks), dim3(256), 0, s, a);     \
+        return hipGetLastError();                                                           \
+    }
+    GPX_VARIANTS(GPX_LAUNCH)
+#undef GPX_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+int batch_blocks_per_cu(int vi) {
+    const VariantDesc& v = kVariants[vi];
+    int n = 0;
+#define GPX_OCC(T, D, FV)                                                                        \
+    if (v.t == T && v.d == D && v.fv == FV) {                                                    \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<T, D, FV>, 256, 0) != hipSuccess) n = 1; \
+    }
+    GPX_VARIANTS(GPX_OCC)
+#undef GPX_OCC
+    return n > 0 ? n : 1;
+}
+
 hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s) {
     if (r.n_prog <= 0) return hipSuccess;
     const uint32_t blocks = (uint32_t)((r.n_prog + 255) / 256);
     hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_jobs(const ReduceArgs* jobs_dev, int32_t n_jobs, int64_t max_prog, hipStream_t s) {
+    if (n_jobs <= 0 || max_prog <= 0) return hipSuccess;
+    const uint32_t bx = (uint32_t)((max_prog + 255) / 256);
+    hipLaunchKernelGGL(k_reduce_jobs, dim3(bx, (uint32_t)n_jobs), dim3(256), 0, s, jobs_dev);
     return hipGetLastError();
 }
 

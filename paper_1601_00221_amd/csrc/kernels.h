@@ -30,12 +30,45 @@ struct EvalArgs {
 struct ReduceArgs {
     const double* partials;
     uint64_t part_base;
-    int64_t stride;             // distance between tiles of one program
+    int64_t stride;             // distance between consecutive blocks of one program
     int64_t n_prog;
     int64_t N;
     void* out;
-    int32_t tiles;
+    int32_t blocks;             // ceil(N / 256)
     int32_t kind;
+};
+
+// Batched evaluation (several jobs over several datasets in one launch).
+struct DatasetDesc {
+    const float* X;
+    const float* y;
+    int64_t N;
+};
+
+struct JobDesc {
+    int32_t ds;                 // dataset index
+    int32_t kind;
+    int32_t n_load;             // features the job's programs read
+    int32_t n_feat_prog;        // feature count register initialisation wraps around
+};
+
+struct UnitDesc {
+    uint32_t job;
+    uint32_t tile;
+    uint32_t q0, q1;            // programs order[q0 .. q1)
+};
+
+struct BatchArgs {
+    const uint32_t* code;
+    const DevProg* progs;
+    const uint32_t* order;
+    const UnitDesc* units;
+    const JobDesc* jobs;
+    const DatasetDesc* datasets;
+    double* partials;
+    uint32_t* counter;          // next unit (persistent form)
+    int32_t n_units;
+    int32_t persistent;
 };
 
 struct VariantDesc {
@@ -52,5 +85,8 @@ int pick_variant(int n_feat_load, int depth);
 
 hipError_t launch_eval(int variant, const EvalArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& r, hipStream_t s);
+hipError_t launch_batch(int variant, const BatchArgs& a, uint32_t grid_blocks, hipStream_t s);
+hipError_t launch_reduce_jobs(const ReduceArgs* jobs_dev, int32_t n_jobs, int64_t max_prog, hipStream_t s);
+int batch_blocks_per_cu(int variant);
 
 }  // namespace gpx

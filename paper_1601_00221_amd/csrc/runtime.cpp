@@ -375,8 +375,9 @@ gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_
     gp_status st;
     const uint32_t *order, *goff;
     if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
+    const int64_t n_blocks = (N + 255) / 256;
     if (kind != GP_OUT_CASES) {
-        if ((st = w.partials.reserve((size_t)tiles * pd.n_prog * sizeof(double))) != GP_OK) return st;
+        if ((st = w.partials.reserve((size_t)n_blocks * pd.n_prog * sizeof(double))) != GP_OK) return st;
     }
     EvalArgs a;
     memset(&a, 0, sizeof a);
@@ -408,7 +409,7 @@ gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_
     r.n_prog = pd.n_prog;
     r.N = N;
     r.out = out;
-    r.tiles = tiles;
+    r.blocks = (int32_t)n_blocks;
     r.kind = kind;
     e = launch_reduce(r, s);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "reduction launch: %s", hipGetErrorString(e));

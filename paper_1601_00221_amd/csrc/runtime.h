@@ -85,6 +85,10 @@ struct EvalOptions {
 
 Workspace& workspace(hipStream_t s);
 
+// Kernel timing brackets (active only while gp_timing_enable(1)).
+hipError_t timed_launch_begin(hipStream_t s, int* slot);
+hipError_t timed_launch_end(hipStream_t s, int slot);
+
 gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t P, int32_t n_feat,
                      ProgData& pd);
 gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
