@@ -275,6 +275,21 @@ typedef struct {
 gp_status gp_lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat,
                         uint32_t* words, int64_t max_words, gp_lower_stats* stats);
 
+/* Translate programs into the instruction stream of kernel variant
+ * `variant`'s interpreter core, taking its handler table to start at
+ * table_base (64-byte aligned; the library finds the real address on the
+ * device itself).  Host only.  Each core instruction is 4 uint32 words:
+ * handler address (2 words), operand offsets, constant.  words (may be
+ * NULL) receives n_words words if max_words allows; prog_off (may be NULL)
+ * receives n_prog + 1 word offsets. */
+gp_status gp_core_lower_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog,
+                             int32_t n_feat, int32_t variant, uint64_t table_base, uint32_t* words,
+                             int64_t max_words, int64_t* prog_off, int64_t* n_words);
+gp_status gp_core_lower_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
+                               int32_t n_prog, int32_t n_reg, int32_t n_feat, int32_t variant,
+                               uint64_t table_base, uint32_t* words, int64_t max_words, int64_t* prog_off,
+                               int64_t* n_words);
+
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------ */

@@ -76,6 +76,8 @@ def lib():
             "gp_serve_release": [P, C.c_uint64],
             "gp_serve_stats": [P, P],
             "gp_serve_destroy": [P],
+            "gp_core_lower_tree": [P, P, P, i32, i32, i32, C.c_uint64, P, i64, P, P],
+            "gp_core_lower_linear": [P, P, P, P, i32, i32, i32, i32, C.c_uint64, P, i64, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -395,6 +397,30 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def core_lower(pop, n_feat, variant, table_base):
+    """Core instruction words (uint32, 4 per instruction) and per-program word
+    offsets of a synth.TreePop / synth.LinearPop for a kernel variant whose
+    handler table is taken to start at table_base (host only)."""
+    L = lib()
+    nw = C.c_int64()
+    prog_off = np.zeros(pop.n_prog + 1, np.int64)
+    if hasattr(pop, "tok"):
+        a = [np.ascontiguousarray(pop.tok, np.int32), np.ascontiguousarray(pop.cst, np.float32),
+             np.ascontiguousarray(pop.off, np.int64)]
+        args = [x.ctypes.data for x in a] + [pop.n_prog, n_feat, variant, table_base]
+        check(L.gp_core_lower_tree(*args, None, 0, None, C.byref(nw)))
+        words = np.zeros(nw.value, np.uint32)
+        check(L.gp_core_lower_tree(*args, words.ctypes.data, len(words), prog_off.ctypes.data, C.byref(nw)))
+    else:
+        a = [np.ascontiguousarray(pop.code, np.uint32), np.ascontiguousarray(pop.off, np.int64),
+             np.ascontiguousarray(pop.cst, np.float32), np.ascontiguousarray(pop.cst_off, np.int64)]
+        args = [x.ctypes.data for x in a] + [pop.n_prog, pop.n_reg, n_feat, variant, table_base]
+        check(L.gp_core_lower_linear(*args, None, 0, None, C.byref(nw)))
+        words = np.zeros(nw.value, np.uint32)
+        check(L.gp_core_lower_linear(*args, words.ctypes.data, len(words), prog_off.ctypes.data, C.byref(nw)))
+    return words, prog_off
 
 
 def out_tensor(kind, n_prog, n_cases, device="cuda"):

@@ -17,10 +17,11 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
+GEN = os.path.join(BUILD, "gen")
 LIB = os.path.join(PKG, "libgp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["lower.cpp", "runtime.cpp", "batch.cpp", "serve.cpp", "eval_kernels.hip"]
+SOURCES = ["lower.cpp", "runtime.cpp", "batch.cpp", "serve.cpp", "core_host.cpp", "core_kernels.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -28,12 +29,40 @@ FLAGS = [
     "-ffp-contract=off",
     # packed FP32 (v_pk_*_f32) stays off; the flag is for the device pass only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-inline-asm",   # the core names the VGPRs it owns, which the compiler reserves
 ]
+
+# The core owns v[NCV ...]; the compiler must never allocate them.  The kernel
+# attribute that caps the compiler's VGPRs is checked by compiling the core
+# with inline-asm warnings on: every clobbered VGPR the core owns must be
+# reported as reserved.
+import re
+
+
+def _check_reserved(src: str):
+    sys.path.insert(0, CSRC)
+    try:
+        import gen_core
+    finally:
+        sys.path.pop(0)
+    flags = [f for f in FLAGS if f != "-Wno-inline-asm"]
+    cmd = [HIPCC, *flags, "-I", GEN, "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", os.devnull]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    reserved = set()
+    for m in re.finditer(r"clobber list contains reserved registers: ([^\[]*)", r.stderr):
+        reserved.update(x.strip() for x in m.group(1).split(","))
+    for t, d, nf in gen_core.VARIANTS:
+        end = gen_core.NCV + max(gen_core.LIN_REGS, d) * t + nf * t
+        missing = [n for n in range(gen_core.NCV, end) if "v%d" % n not in reserved]
+        if missing:
+            raise RuntimeError("the compiler may allocate core VGPRs %s (variant %s)" % (missing[:8], (t, d, nf)))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, "-I", GEN, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
@@ -42,9 +71,18 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    # generate the hand-written interpreter core for every kernel variant
+    sys.path.insert(0, CSRC)
+    try:
+        import gen_core
+    finally:
+        sys.path.pop(0)
+    gen_core.main(GEN)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
+        check = ex.submit(_check_reserved, "core_kernels.hip")
         objs = list(ex.map(_compile, srcs))
+        check.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -16,7 +16,8 @@
 
 #include "../../include/gp.h"
 #include "batch.h"
-#include "kernels.h"
+#include "core_host.h"
+#include "core_kernels.h"
 #include "runtime.h"
 
 namespace gpx {
@@ -33,13 +34,13 @@ static int device_cus() {
     return cus;
 }
 
-// Smallest-depth compiled variant with tile width t able to hold the batch.
+// Smallest compiled variant with tile width t able to hold the batch.
 static int variant_for_t(int t, int n_load, int depth) {
     int best = -1;
-    for (int i = 0; i < n_variants(); i++) {
-        const VariantDesc& v = variant(i);
-        if (v.t != t || v.fv < n_load || v.d < depth) continue;
-        if (best < 0 || v.d * 1000 + v.fv < variant(best).d * 1000 + variant(best).fv) best = i;
+    for (int i = 0; i < core_variants(); i++) {
+        if (core_variant_t(i) != t || core_variant_nf(i) < n_load || core_variant_d(i) < depth) continue;
+        const int key = core_variant_d(i) * 1000 + core_variant_nf(i);
+        if (best < 0 || key < core_variant_d(best) * 1000 + core_variant_nf(best)) best = i;
     }
     return best;
 }
@@ -53,20 +54,16 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
         depth = std::max(depth, j.pd->max_depth);
     }
     const int vi = cfg.variant;
-    if (vi < 0 || vi >= n_variants()) return fail(GP_E_INVAL, "kernel variant %d does not exist", vi);
-    const VariantDesc& v = variant(vi);
-    if (v.fv < n_load || v.d < depth)
-        return fail(GP_E_INVAL, "variant %d (fv %d, depth %d) cannot hold %d features / depth %d", vi, v.fv, v.d,
-                    n_load, depth);
+    if (vi < 0 || vi >= core_variants()) return fail(GP_E_INVAL, "kernel variant %d does not exist", vi);
+    const int vt = core_variant_t(vi);
+    if (core_variant_nf(vi) < n_load || core_variant_d(vi) < depth)
+        return fail(GP_E_INVAL, "variant %d (%d features, depth %d) cannot hold %d features / depth %d", vi,
+                    core_variant_nf(vi), core_variant_d(vi), n_load, depth);
     plan.vi = vi;
     const int32_t unit_prog = std::max(1, cfg.unit_programs);
-    int64_t code_words = 0, n_prog = 0;
-    for (const BatchJobRef& j : jobs) {
-        code_words += (int64_t)j.pd->code.size();
-        n_prog += j.pd->n_prog;
-    }
-    if (code_words > 0xFFFFFFFFll || n_prog > 0x7FFFFFFFll) return fail(GP_E_INVAL, "batch too large");
-    plan.code.reserve((size_t)code_words);
+    int64_t n_prog = 0;
+    for (const BatchJobRef& j : jobs) n_prog += j.pd->n_prog;
+    if (n_prog > 0x7FFFFFFFll) return fail(GP_E_INVAL, "batch too large");
     plan.progs.reserve((size_t)n_prog);
     plan.order.reserve((size_t)n_prog);
     uint64_t part_base = 0;
@@ -77,12 +74,17 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
         const gp_dataset& d = ds[j.ds];
         const int64_t N = d.n_cases;
         const int64_t blocks = (N + 255) / 256;
-        const int64_t tiles = (N + 64LL * v.t - 1) / (64LL * v.t);
+        const int64_t tiles = (N + 64LL * vt - 1) / (64LL * vt);
+        std::vector<uint32_t> jcode;
+        std::vector<DevProg> jprogs;
+        gp_status st = core_translate(pd, vi, jcode, jprogs);
+        if (st != GP_OK) return st;
+        if ((plan.code.size() + jcode.size()) * 4 > 0xFFFFFFF0ull) return fail(GP_E_INVAL, "batch code exceeds 4 GiB");
         const uint32_t code_base = (uint32_t)plan.code.size();
         const uint32_t prog_base = (uint32_t)plan.progs.size();
-        plan.code.insert(plan.code.end(), pd.code.begin(), pd.code.end());
+        plan.code.insert(plan.code.end(), jcode.begin(), jcode.end());
         for (int32_t p = 0; p < pd.n_prog; p++) {
-            DevProg dp = pd.progs[p];
+            DevProg dp = jprogs[p];
             dp.code_off += code_base;
             dp.part_base = part_base + (uint64_t)p;
             dp.part_stride = (uint32_t)pd.n_prog;
@@ -117,10 +119,10 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
             }
         }
         JobDesc jd;
+        memset(&jd, 0, sizeof jd);
         jd.ds = j.ds;
         jd.kind = j.kind;
         jd.n_load = pd.n_load;
-        jd.n_feat_prog = pd.n_feat;
         plan.jobs.push_back(jd);
         ReduceArgs r;
         memset(&r, 0, sizeof r);
@@ -190,7 +192,8 @@ gp_status upload_plan(BatchPlan& p, BatchScratch& sc, hipStream_t s) {
 }
 
 gp_status launch_plan(const BatchPlan& p, BatchScratch& sc, hipStream_t s) {
-    BatchArgs a;
+    if (p.units.empty()) return GP_OK;
+    CoreArgs a;
     memset(&a, 0, sizeof a);
     a.code = (const uint32_t*)sc.code.p;
     a.progs = (const DevProg*)sc.progs.p;
@@ -202,13 +205,16 @@ gp_status launch_plan(const BatchPlan& p, BatchScratch& sc, hipStream_t s) {
     a.counter = (uint32_t*)sc.counter.p;
     a.n_units = (int32_t)p.units.size();
     a.persistent = p.persistent ? 1 : 0;
-    const uint32_t grid = (uint32_t)(device_cus() * batch_blocks_per_cu(p.vi));
+    const uint32_t grid = p.persistent ? (uint32_t)(device_cus() * core_blocks_per_cu(p.vi))
+                                       : (uint32_t)((p.units.size() + 3) / 4);
     int slot;
-    hipError_t e = timed_launch_begin(s, &slot);
-    if (e == hipSuccess) e = launch_batch(p.vi, a, grid, s);
+    hipError_t e = hipSuccess;
+    if (p.persistent) e = core_zero_counter(a.counter, s);
+    if (e == hipSuccess) e = timed_launch_begin(s, &slot);
+    if (e == hipSuccess) e = core_launch(p.vi, a, grid, s);
     if (e == hipSuccess) e = timed_launch_end(s, slot);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "batch launch: %s", hipGetErrorString(e));
-    e = launch_reduce_jobs((const ReduceArgs*)sc.reduce.p, (int32_t)p.reduce.size(), p.max_prog, s);
+    e = core_reduce_jobs((const ReduceArgs*)sc.reduce.p, (int32_t)p.reduce.size(), p.max_prog, s);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "batch reduction launch: %s", hipGetErrorString(e));
     return GP_OK;
 }
@@ -285,8 +291,10 @@ static std::string batch_key(const std::vector<BatchJobRef>& jobs, const std::ve
 
 static gp_status time_config(const std::vector<BatchJobRef>& jobs, const std::vector<gp_dataset>& ds,
                              const gp_batch_config& c, int reps, BatchScratch& sc, hipStream_t s, double* ms) {
+    gp_status st = core_ready(c.variant, s);
+    if (st != GP_OK) return st;
     BatchPlan plan;
-    gp_status st = plan_batch(jobs, ds, c, plan);
+    st = plan_batch(jobs, ds, c, plan);
     if (st != GP_OK) return st;
     if ((st = upload_plan(plan, sc, s)) != GP_OK) return st;
     if ((st = launch_plan(plan, sc, s)) != GP_OK) return st;  // warm-up
@@ -324,8 +332,9 @@ gp_status tune_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
         depth = std::max(depth, j.pd->max_depth);
     }
     std::vector<int> widths;
-    for (int i = 0; i < n_variants(); i++)
-        if (std::find(widths.begin(), widths.end(), variant(i).t) == widths.end()) widths.push_back(variant(i).t);
+    for (int i = 0; i < core_variants(); i++)
+        if (std::find(widths.begin(), widths.end(), core_variant_t(i)) == widths.end())
+            widths.push_back(core_variant_t(i));
     double best_t = 1e300;
     gp_batch_config b;
     memset(&b, 0, sizeof b);
@@ -378,7 +387,7 @@ gp_batch_config default_config(const std::vector<BatchJobRef>& jobs) {
     }
     gp_batch_config c;
     memset(&c, 0, sizeof c);
-    c.variant = pick_variant(n_load, depth);
+    c.variant = pick_core_variant(n_load, depth);
     c.unit_programs = 32;
     c.persistent = 1;
     return c;
@@ -475,6 +484,7 @@ gp_status gp_eval_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
     if (cfg) c = *cfg;
     else if (!tuned_config(refs, dv, &c)) c = default_config(refs);
     if (c.variant < 0) return fail(GP_E_DEPTH, "no kernel variant can hold these programs");
+    if ((st = core_ready(c.variant, s)) != GP_OK) return st;
     BatchPlan plan;
     if ((st = plan_batch(refs, dv, c, plan)) != GP_OK) return st;
     if ((st = upload_plan(plan, sc, s)) != GP_OK) return st;
@@ -497,14 +507,14 @@ gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
     return tune_batch(refs, dv, reps < 1 ? 3 : reps, sc, s, best, best_ms);
 }
 
-int32_t gp_num_variants(void) { return n_variants(); }
+int32_t gp_num_variants(void) { return core_variants(); }
 
 gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat) {
     clear_error();
-    if (i < 0 || i >= n_variants()) return fail(GP_E_INVAL, "variant %d does not exist", i);
-    if (t) *t = variant(i).t;
-    if (depth) *depth = variant(i).d;
-    if (n_feat) *n_feat = variant(i).fv;
+    if (i < 0 || i >= core_variants()) return fail(GP_E_INVAL, "variant %d does not exist", i);
+    if (t) *t = core_variant_t(i);
+    if (depth) *depth = core_variant_d(i);
+    if (n_feat) *n_feat = core_variant_nf(i);
     return GP_OK;
 }
 

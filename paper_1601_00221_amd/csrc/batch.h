@@ -8,7 +8,7 @@
 #include <vector>
 
 #include "../../include/gp.h"
-#include "kernels.h"
+#include "core_kernels.h"
 #include "runtime.h"
 
 namespace gpx {

@@ -1,0 +1,312 @@
+// Host side of the interpreter core: find each kernel variant's handler
+// table on the device, and translate lowered programs into core
+// instructions (handler address, operand offsets, constant).
+#include <hip/hip_runtime_api.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gp.h"
+#include "core_host.h"
+#include "core_kernels.h"
+#include "gp_internal.h"
+#include "runtime.h"
+
+namespace gpx {
+#include "core_gen.inc"
+
+namespace {
+
+struct VariantMap {
+    bool ready = false;
+    int device = -1;
+    uint64_t base = 0;
+    std::unordered_map<uint32_t, uint16_t> slot;
+};
+
+std::mutex g_mu;
+std::vector<VariantMap> g_maps;
+
+uint32_t key_of(int kind, int op, int p1, int p2) {
+    return (uint32_t)kind | ((uint32_t)op << 8) | ((uint32_t)(uint8_t)(int8_t)p1 << 16) |
+           ((uint32_t)(uint8_t)(int8_t)p2 << 24);
+}
+
+}  // namespace
+
+const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
+int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
+int core_reg_levels(int vi) { return kCoreVariants[vi].d > GPX_LIN_REGS ? kCoreVariants[vi].d : GPX_LIN_REGS; }
+
+int pick_core_variant(int n_load, int depth) {
+    // widest tile first; among those the fewest handlers (least code)
+    int best = -1;
+    for (int i = 0; i < core_variants(); i++) {
+        const CoreVariantDesc& v = kCoreVariants[i];
+        if (v.nf < n_load || v.d < depth) continue;
+        if (best < 0) { best = i; continue; }
+        const CoreVariantDesc& b = kCoreVariants[best];
+        if (v.t > b.t || (v.t == b.t && (v.nf < b.nf || (v.nf == b.nf && v.n < b.n)))) best = i;
+    }
+    return best;
+}
+
+gp_status core_ready(int vi, hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> g(g_mu);
+    if ((int)g_maps.size() < core_variants()) g_maps.resize(core_variants());
+    VariantMap& m = g_maps[vi];
+    if (m.ready && m.device == dev) return GP_OK;
+    uint64_t* d = nullptr;
+    e = hipMalloc(&d, 256);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e));
+    CoreArgs a;
+    memset(&a, 0, sizeof a);
+    a.probe = 1;
+    a.probe_out = d;
+    e = core_launch(vi, a, 1, s);
+    uint64_t base = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&base, d, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(d);
+    if (e != hipSuccess) return fail(GP_E_DEVICE, "handler table probe: %s", hipGetErrorString(e));
+    if (base == 0 || (base & (GPX_SLOT - 1)) != 0) return fail(GP_E_DEVICE, "handler table probe returned %llx",
+                                                               (unsigned long long)base);
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    m.slot.clear();
+    for (int i = 0; i < v.n; i++) m.slot[key_of(v.keys[i].kind, v.keys[i].op, v.keys[i].p1, v.keys[i].p2)] = v.slots[i];
+    m.base = base;
+    m.device = dev;
+    m.ready = true;
+    return GP_OK;
+}
+
+namespace {
+
+struct Emitter {
+    const VariantMap& m;
+    std::vector<uint32_t>& out;
+    char* err;
+    bool ok = true;
+
+    void put(int kind, int op, int p1, int p2, uint32_t pay, uint32_t cst) {
+        auto it = m.slot.find(key_of(kind, op, p1, p2));
+        if (it == m.slot.end()) {
+            snprintf(err, 256, "no core handler for kind %d op %d (%d, %d)", kind, op, p1, p2);
+            ok = false;
+            return;
+        }
+        const uint64_t addr = m.base + (uint64_t)it->second * GPX_SLOT;
+        out.push_back((uint32_t)addr);
+        out.push_back((uint32_t)(addr >> 32));
+        out.push_back(pay);
+        out.push_back(cst);
+    }
+    // leave the core: operation op on A (offset or constant), B, into D
+    void exit(uint32_t op, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
+        const uint32_t fl = (a_const ? 1u : 0u) | (b_const ? 2u : 0u);
+        put(CK_EXIT, 0, 0, 0,
+            (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16) |
+                ((op | (fl << 4)) << 24),
+            cst);
+    }
+};
+
+bool is_core_op(uint32_t op) { return op == GP_ADD || op == GP_SUB || op == GP_MUL; }
+
+}  // namespace
+
+static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const VariantMap& m, std::vector<uint32_t>& out,
+                          char* err) {
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    const int T = v.t, FO = core_reg_levels(vi) * T;
+    Emitter e{m, out, err};
+    for (int64_t i = 0; i < n_instr && e.ok; i++) {
+        const uint32_t w0 = w[2 * i], c = w[2 * i + 1];
+        const uint32_t op = w0 & 15u, mode = (w0 >> 4) & 15u;
+        const int fa = (int)((w0 >> 8) & 255u), fb = (int)((w0 >> 16) & 255u), ha = (int)(w0 >> 24);
+        int h;  // stack height before the instruction
+        switch (mode) {
+            case M_SS: case M_SSR: h = ha + 1; break;
+            case M_XX: case M_XC: case M_CX: case M_X: case M_C: h = ha - 1; break;
+            default: h = ha; break;
+        }
+        const int xa = FO + fa * T, xb = FO + fb * T;
+        if (op == OP_PUSH) {
+            if (mode == M_X) {
+                if (h != 0) { snprintf(err, 256, "push of a variable above the stack bottom"); return GP_E_INVAL; }
+                e.put(CK_PUSHX, 0, 0, 0, (uint32_t)xa, 0);
+            } else {
+                e.put(CK_PUSHC, 0, 0, 0, (uint32_t)(h * T), c);
+            }
+            continue;
+        }
+        if (is_core_op(op)) {
+            const bool comm = op != GP_SUB;
+            switch (mode) {
+                case M_SS: e.put(CK_SS, op, 0, 0, (uint32_t)((h - 2) * T), 0); break;
+                case M_SSR:
+                    if (comm) e.put(CK_SS, op, 0, 0, (uint32_t)((h - 2) * T), 0);
+                    else e.put(CK_SSR, op, 0, 0, (uint32_t)((h - 2) * T), 0);
+                    break;
+                case M_SX: e.put(CK_SX, op, h - 1, 0, (uint32_t)xb, 0); break;
+                case M_XS:
+                    if (comm) e.put(CK_SX, op, h - 1, 0, (uint32_t)xa, 0);
+                    else e.put(CK_XS, op, h - 1, 0, (uint32_t)xa, 0);
+                    break;
+                case M_SC: e.put(CK_SC, op, 0, 0, (uint32_t)((h - 1) * T), c); break;
+                case M_CS:
+                    if (comm) e.put(CK_SC, op, 0, 0, (uint32_t)((h - 1) * T), c);
+                    else e.put(CK_CS, op, 0, 0, (uint32_t)((h - 1) * T), c);
+                    break;
+                case M_XX:
+                    if (v.nf <= 8) {
+                        if (comm) {
+                            const int a = fa < fb ? fa : fb, b = fa < fb ? fb : fa;
+                            e.put(CK_XX, op, h, b - a, (uint32_t)(a * T), 0);
+                        } else {
+                            e.put(CK_XX, op, h, fb - fa, (uint32_t)(fa * T), 0);
+                        }
+                    } else {
+                        e.put(CK_XX2, op, h, 0, (uint32_t)xa | ((uint32_t)xb << 8), 0);
+                    }
+                    break;
+                case M_XC: e.put(CK_XC, op, h, 0, (uint32_t)xa, c); break;
+                case M_CX:
+                    if (comm) e.put(CK_XC, op, h, 0, (uint32_t)xb, c);
+                    else e.put(CK_CX, op, h, 0, (uint32_t)xb, c);
+                    break;
+                default:
+                    snprintf(err, 256, "mode %u is not a binary mode", mode);
+                    return GP_E_INVAL;
+            }
+            continue;
+        }
+        // protected division and the transcendentals leave the core
+        switch (mode) {
+            case M_SS: e.exit(op, (h - 2) * T, (h - 1) * T, (h - 2) * T, false, false, 0); break;
+            case M_SSR: e.exit(op, (h - 1) * T, (h - 2) * T, (h - 2) * T, false, false, 0); break;
+            case M_SX: e.exit(op, (h - 1) * T, xb, (h - 1) * T, false, false, 0); break;
+            case M_XS: e.exit(op, xa, (h - 1) * T, (h - 1) * T, false, false, 0); break;
+            case M_SC: e.exit(op, (h - 1) * T, 0, (h - 1) * T, false, true, c); break;
+            case M_CS: e.exit(op, 0, (h - 1) * T, (h - 1) * T, true, false, c); break;
+            case M_XX: e.exit(op, xa, xb, h * T, false, false, 0); break;
+            case M_XC: e.exit(op, xa, 0, h * T, false, true, c); break;
+            case M_CX: e.exit(op, 0, xb, h * T, true, false, c); break;
+            case M_S: e.exit(op, (h - 1) * T, 0, (h - 1) * T, false, false, 0); break;
+            case M_X: e.exit(op, xa, 0, h * T, false, false, 0); break;
+            default: e.exit(op, 0, 0, h * T, true, false, c); break;  // M_C
+        }
+    }
+    if (e.ok) e.exit(CORE_OP_END, 0, 0, 0, false, false, 0);
+    return e.ok ? GP_OK : GP_E_INVAL;
+}
+
+static int translate_linear(const uint32_t* w, int64_t n, const uint32_t* cst, int32_t n_reg, int32_t n_feat, int vi,
+                            const VariantMap& m, std::vector<uint32_t>& out, char* err) {
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    const int T = v.t, FO = core_reg_levels(vi) * T;
+    Emitter e{m, out, err};
+    auto off = [&](int id) { return id < n_reg ? id * T : FO + (id - n_reg) * T; };
+    // registers start as r[k] = x[k mod n_feat]
+    for (int k = 0; k < n_reg && e.ok; k++) e.put(CK_MOVX, 0, k, 0, (uint32_t)(FO + (k % n_feat) * T), 0);
+    for (int64_t i = 0; i < n && e.ok; i++) {
+        const uint32_t wd = w[i];
+        const uint32_t op = wd & 255u;
+        const int d = (int)((wd >> 8) & 255u), s1 = (int)((wd >> 16) & 255u), s2 = (int)(wd >> 24);
+        const bool c1 = s1 >= GP_SRC_CONST, c2 = s2 >= GP_SRC_CONST;
+        const uint32_t v1 = c1 ? cst[s1 - GP_SRC_CONST] : 0u, v2 = c2 ? cst[s2 - GP_SRC_CONST] : 0u;
+        if (op >= GP_SIN) {  // unary: leave the core
+            e.exit(op, c1 ? 0 : off(s1), 0, d * T, c1, false, v1);
+            continue;
+        }
+        if (op == GP_PDIV) {
+            if (c1 && c2) {
+                e.put(CK_MOVC, 0, d, 0, 0, v1);
+                e.exit(op, d * T, 0, d * T, false, true, v2);
+            } else {
+                e.exit(op, c1 ? 0 : off(s1), c2 ? 0 : off(s2), d * T, c1, c2, c1 ? v1 : v2);
+            }
+            continue;
+        }
+        const bool comm = op != GP_SUB;
+        if (c1 && c2) {
+            e.put(CK_MOVC, 0, d, 0, 0, v1);
+            if (comm) e.put(CK_CR, op, d, 0, (uint32_t)(d * T), v2);
+            else e.put(CK_RC, op, d, 0, (uint32_t)(d * T), v2);
+        } else if (c1) {
+            e.put(CK_CR, op, d, 0, (uint32_t)off(s2), v1);
+        } else if (c2) {
+            if (comm) e.put(CK_CR, op, d, 0, (uint32_t)off(s1), v2);
+            else e.put(CK_RC, op, d, 0, (uint32_t)off(s1), v2);
+        } else if (s1 < n_reg) {
+            e.put(CK_RR, op, d, s1, (uint32_t)off(s2), 0);
+        } else if (s2 < n_reg) {
+            if (comm) e.put(CK_RR, op, d, s2, (uint32_t)off(s1), 0);
+            else e.put(CK_XR, op, d, s2, (uint32_t)off(s1), 0);
+        } else {
+            e.put(CK_FF, op, d, 0, (uint32_t)off(s1) | ((uint32_t)off(s2) << 8), 0);
+        }
+    }
+    if (e.ok) e.exit(CORE_OP_END, 0, 0, 0, false, false, 0);
+    return e.ok ? GP_OK : GP_E_INVAL;
+}
+
+static VariantMap map_at(int vi, uint64_t base) {
+    VariantMap m;
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    for (int i = 0; i < v.n; i++) m.slot[key_of(v.keys[i].kind, v.keys[i].op, v.keys[i].p1, v.keys[i].p2)] = v.slots[i];
+    m.base = base;
+    m.ready = true;
+    return m;
+}
+
+static gp_status translate_with(const ProgData& pd, int vi, const VariantMap& m, std::vector<uint32_t>& code,
+                                std::vector<DevProg>& progs) {
+    code.clear();
+    progs = pd.progs;
+    char err[256];
+    for (int32_t p = 0; p < pd.n_prog; p++) {
+        const DevProg& src = pd.progs[p];
+        const size_t start = code.size();
+        int rc;
+        if ((src.meta & 1u) == FORM_TREE)
+            rc = translate_tree(pd.code.data() + src.code_off, src.len, vi, m, code, err);
+        else
+            rc = translate_linear(pd.code.data() + src.code_off, src.len, pd.code.data() + src.code_off + src.len,
+                                  pd.n_reg, pd.n_feat, vi, m, code, err);
+        if (rc != GP_OK) return fail((gp_status)rc, "program %d: %s", p, err);
+        if (code.size() * 4 > 0xFFFFFFF0ull) return fail(GP_E_INVAL, "programs exceed 4 GiB of core code");
+        progs[p].code_off = (uint32_t)start;   // words
+        progs[p].len = (uint32_t)((code.size() - start) / 4);
+    }
+    return GP_OK;
+}
+
+gp_status core_translate(const ProgData& pd, int vi, std::vector<uint32_t>& code, std::vector<DevProg>& progs) {
+    VariantMap m;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        if ((int)g_maps.size() <= vi || !g_maps[vi].ready) return fail(GP_E_DEVICE, "core variant %d not probed", vi);
+        m = g_maps[vi];
+    }
+    return translate_with(pd, vi, m, code, progs);
+}
+
+gp_status core_translate_at(const ProgData& pd, int vi, uint64_t base, std::vector<uint32_t>& code,
+                            std::vector<DevProg>& progs) {
+    if (vi < 0 || vi >= core_variants()) return fail(GP_E_INVAL, "variant %d does not exist", vi);
+    if (base & (GPX_SLOT - 1)) return fail(GP_E_INVAL, "table base must be %d-byte aligned", GPX_SLOT);
+    return translate_with(pd, vi, map_at(vi, base), code, progs);
+}
+
+int core_variant_t(int vi) { return kCoreVariants[vi].t; }
+int core_variant_d(int vi) { return kCoreVariants[vi].d; }
+int core_variant_nf(int vi) { return kCoreVariants[vi].nf; }
+
+}  // namespace gpx

@@ -1,0 +1,31 @@
+// Host side of the interpreter core (core_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/gp.h"
+#include "gp_internal.h"
+#include "runtime.h"
+
+namespace gpx {
+
+int core_variants();
+int core_variant_t(int vi);        // case slots per lane
+int core_variant_d(int vi);        // stack levels
+int core_variant_nf(int vi);       // feature slots
+int core_reg_levels(int vi);       // register/stack levels before the features
+// Widest-tile variant able to hold n_load features and `depth` levels, or -1.
+int pick_core_variant(int n_load, int depth);
+// Locate the variant's handler table on the current device (one probe launch
+// on stream s the first time).
+gp_status core_ready(int vi, hipStream_t s);
+// Core instructions and per-program records of lowered programs.
+gp_status core_translate(const ProgData& pd, int vi, std::vector<uint32_t>& code, std::vector<DevProg>& progs);
+// The same with the handler table taken to start at `base` (no device needed).
+gp_status core_translate_at(const ProgData& pd, int vi, uint64_t base, std::vector<uint32_t>& code,
+                            std::vector<DevProg>& progs);
+
+}  // namespace gpx

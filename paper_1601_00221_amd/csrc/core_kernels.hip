@@ -1,0 +1,334 @@
+// Evaluation kernel built around the hand-written interpreter core
+// (gen_core.py).  One wavefront owns a case tile of 64 lanes x T slots
+// (slot j of lane l is case tile*64*T + j*64 + l, so every feature row is
+// read with contiguous 256-byte accesses, as the paper strides a thread's
+// cases by the thread count, section 4.1).  The tile's features are loaded
+// once into the core's VGPR range; then the wave interprets its programs on
+// it.  The two-dimensional stack (section 4) is that VGPR range: one decoded
+// instruction updates T slots of 64 lanes.
+//
+// Work the asm core leaves to the compiled code: protected division and
+// sin/cos/exp/log (an exit carries the operand and destination offsets; the
+// kernel moves the T slots out, computes, moves them back) and the end of a
+// program.  sin, cos, exp and log are evaluated in binary64 and rounded
+// once: random GP trees chain many of them, and most such programs turn a
+// last-place difference into a visible fitness difference, so a binary32
+// library result would make fitness depend on the evaluator.
+//
+// Fitness: per-slot error terms in binary32, per-lane binary64 sums over the
+// 4 slots of each 256-case block, a fixed wavefront butterfly, one partial
+// per (program, block), then a fixed-order reduction over blocks -- the
+// result does not depend on the tile width, the grouping, or what else
+// shared the launch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gp.h"
+#include "core_kernels.h"
+#include "gp_internal.h"
+
+namespace gpx {
+#include "core_gen.inc"
+
+template <int N> using fvec_t = float __attribute__((ext_vector_type(N)));
+// Values indexed by a wave-uniform loop counter: with more than 8 elements the
+// compiler selects them with one s_set_gpr_idx move (smaller vectors become
+// compare/select chains).
+template <int T> using ivec_t = fvec_t<(T < 9 ? 9 : T)>;
+
+__device__ __forceinline__ float pdiv(float a, float b) { return (fabsf(b) < 1e-6f) ? 1.0f : a / b; }
+__device__ __forceinline__ float gsin(float a) { return (float)sin((double)a); }
+__device__ __forceinline__ float gcos(float a) { return (float)cos((double)a); }
+__device__ __forceinline__ float expc(float a) {
+    const float t = (a > 88.0f) ? 88.0f : a;  // a NaN fails the compare and passes through
+    return (float)exp((double)t);
+}
+__device__ __forceinline__ float plog(float a) {
+    const float m = fabsf(a);
+    return (m < 1e-6f) ? 0.0f : (float)log((double)m);
+}
+
+// Exit payload: byte 0 offset of A, byte 1 offset of B, byte 2 offset of the
+// destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
+// the constant, bit 5: B is the constant).
+template <int T>
+__device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
+    const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
+    const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
+    const float c = __uint_as_float(cbits);
+    if (op == GP_PDIV) {
+        float A[T], B[T];
+        if (fl & 1u) {
+#pragma unroll
+            for (int j = 0; j < T; j++) A[j] = c;
+        } else {
+            core_gather<T>(oa, A);
+        }
+        if (fl & 2u) {
+#pragma unroll
+            for (int j = 0; j < T; j++) B[j] = c;
+        } else {
+            core_gather<T>(ob, B);
+        }
+#pragma unroll
+        for (int j = 0; j < T; j++) A[j] = pdiv(A[j], B[j]);
+        core_scatter<T>(od, A);
+        return;
+    }
+    float A[T];
+    if (fl & 1u) {
+#pragma unroll
+        for (int j = 0; j < T; j++) A[j] = c;
+    } else {
+        core_gather<T>(oa, A);
+    }
+    // one copy of each long function, applied slot by slot
+    ivec_t<T> a;
+#pragma unroll
+    for (int j = 0; j < T; j++) a[j] = A[j];
+    switch (op) {
+        case GP_SIN:
+#pragma unroll 1
+            for (int j = 0; j < T; j++) a[j] = gsin(a[j]);
+            break;
+        case GP_COS:
+#pragma unroll 1
+            for (int j = 0; j < T; j++) a[j] = gcos(a[j]);
+            break;
+        case GP_EXPC:
+#pragma unroll 1
+            for (int j = 0; j < T; j++) a[j] = expc(a[j]);
+            break;
+        default:  // GP_PLOG
+#pragma unroll 1
+            for (int j = 0; j < T; j++) a[j] = plog(a[j]);
+            break;
+    }
+#pragma unroll
+    for (int j = 0; j < T; j++) A[j] = a[j];
+    core_scatter<T>(od, A);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+    return v;
+}
+
+// One work unit: a case tile and the programs order[q0 .. q1).  The kernel
+// has exactly one call site of the core (its labels are unique); in probe
+// mode the core only reports where its handler table starts.
+template <int T, int D, int NF>
+__device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, const float* y, int64_t N,
+                                             int32_t n_load, int32_t kind, uint32_t tile, uint32_t q0,
+                                             uint32_t q1) {
+    static_assert(T % 4 == 0, "a tile holds whole 256-case blocks");
+    constexpr int RB = D > GPX_LIN_REGS ? D : GPX_LIN_REGS;   // register/stack levels before the features
+    const uint32_t lane = threadIdx.x & 63u;
+    const int64_t tile0 = (int64_t)tile * (64 * T);            // first case of the tile (uniform)
+    const int64_t left = N - tile0;                            // cases from the tile start to the end
+    const int64_t n_blocks = (N + 255) / 256;
+    // slot j of this lane is case tile0 + 64 j + lane; it exists if 64 j + lane < left
+    for (int32_t f = 0; f < n_load; f++) {
+        const float* row = X + (int64_t)f * N + tile0;         // uniform base, lane offsets
+        float x[T];
+#pragma unroll
+        for (int j = 0; j < T; j++) x[j] = (64 * j + (int64_t)lane < left) ? row[64 * j + lane] : 0.0f;
+        core_scatter<T>((uint32_t)(RB * T + f * T), x);
+    }
+    const uint64_t code = (uint64_t)a.code;
+    for (uint32_t q = q0; q < q1; ++q) {
+        DevProg P;
+        uint32_t off = 0;
+        if (!a.probe) {
+            P = a.progs[__builtin_amdgcn_readfirstlane(a.order[q])];
+            // program records are wave-uniform; keep the core's offset in an SGPR
+            off = __builtin_amdgcn_readfirstlane(P.code_off) * 4u;
+        }
+        for (;;) {
+            uint32_t pay, cst;
+            uint64_t table;
+            Core<T, D, NF>::run(code, off, pay, cst, a.probe, table);
+            if (a.probe) {
+                if (threadIdx.x == 0) a.probe_out[0] = table;
+                return;
+            }
+            if (((pay >> 24) & 15u) == CORE_OP_END) break;
+            do_exit<T>(pay, cst);
+            off += 16u;
+        }
+        float o[T];
+        core_gather<T>(0u, o);
+
+        if (kind == GP_OUT_CASES) {
+            float* row = a.cases_out + (int64_t)P.row * N + tile0;
+#pragma unroll
+            for (int j = 0; j < T; j++)
+                if (64 * j + (int64_t)lane < left) row[64 * j + lane] = o[j];
+            continue;
+        }
+        const float* yt = y + tile0;
+#pragma unroll
+        for (int k = 0; k < T / 4; k++) {
+            const int64_t blk = (int64_t)tile * (T / 4) + k;
+            double v;
+            if (kind == GP_FIT_HITS) {
+                uint32_t hits = 0;
+#pragma unroll
+                for (int j = 4 * k; j < 4 * k + 4; j++) {
+                    const bool ok = 64 * j + (int64_t)lane < left;
+                    const float yj = ok ? yt[64 * j + lane] : 0.0f;
+                    const bool hit = ok && ((o[j] > 0.0f) == (yj > 0.0f));
+                    hits += (uint32_t)__popcll(__ballot(hit));
+                }
+                v = (double)hits;
+            } else {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 4 * k; j < 4 * k + 4; j++) {
+                    const bool ok = 64 * j + (int64_t)lane < left;
+                    const float yj = ok ? yt[64 * j + lane] : 0.0f;
+                    const float d = o[j] - yj;
+                    const float t = (kind == GP_FIT_MSE) ? d * d : fabsf(d);
+                    acc += ok ? (double)t : 0.0;
+                }
+                v = wave_sum(acc);
+            }
+            if (lane == 0 && blk < n_blocks) a.partials[P.part_base + (uint64_t)blk * P.part_stride] = v;
+        }
+    }
+}
+
+// Units come either from a table (batched launches: persistent waves pull
+// them longest first from a counter, or one wave per unit) or implicitly,
+// unit u = (tile u mod tiles, program group u div tiles) over one dataset.
+template <int T, int D, int NF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(GPX_NUM_VGPR_ATTR))) void k_core(CoreArgs a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool table = a.units != nullptr;
+    uint32_t u;
+    if (table) {
+        u = blockIdx.x * 4u + wib;
+    } else {
+        // Blocks go to the 8 XCDs round robin; give each XCD a contiguous
+        // range of units so a program group's code stays in one L2.
+        const uint32_t nb = gridDim.x, b = blockIdx.x;
+        u = ((b & 7u) * (nb >> 3) + (b >> 3)) * 4u + wib;
+    }
+    for (;;) {
+        uint32_t tile = 0, q0 = 0, q1 = 1;
+        const float *X = nullptr, *y = nullptr;
+        int64_t N = 1;
+        int32_t n_load = 0, kind = 0;
+        if (a.probe) {
+            if (u != 0) return;
+        } else if (!table) {
+            if (u >= (uint32_t)a.n_units) return;
+            tile = u % (uint32_t)a.tiles;
+            const uint32_t grp = u / (uint32_t)a.tiles;
+            q0 = a.group_off[grp];
+            q1 = a.group_off[grp + 1];
+            X = a.X;
+            y = a.y;
+            N = a.N;
+            n_load = a.n_load;
+            kind = a.kind;
+        } else {
+            if (a.persistent) {
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(a.counter, 1u);
+                u = __builtin_amdgcn_readfirstlane(t);
+            }
+            if (u >= (uint32_t)a.n_units) return;
+            const UnitDesc ud = a.units[u];
+            const JobDesc jd = a.jobs[ud.job];
+            const DatasetDesc dd = a.datasets[jd.ds];
+            tile = ud.tile;
+            q0 = ud.q0;
+            q1 = ud.q1;
+            X = dd.X;
+            y = dd.y;
+            N = dd.N;
+            n_load = jd.n_load;
+            kind = jd.kind;
+        }
+        process_unit<T, D, NF>(a, X, y, N, n_load, kind, __builtin_amdgcn_readfirstlane(tile),
+                               __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1));
+        if (a.probe || !table || !a.persistent) return;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
+// Fixed-order reduction over blocks: program p of job j sums
+// partial[base_j + b * stride_j + p] for b = 0 .. blocks_j - 1.
+__global__ __launch_bounds__(256) void k_reduce_jobs(const ReduceArgs* jobs) {
+    const ReduceArgs r = jobs[blockIdx.y];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= r.n_prog) return;
+    const double* src = r.partials + r.part_base + p;
+    double s = 0.0;
+    for (int32_t t = 0; t < r.blocks; t++) s += src[(int64_t)t * r.stride];
+    if (r.kind == GP_FIT_HITS) ((int32_t*)r.out)[p] = (int32_t)s;
+    else if (r.kind == GP_FIT_MSE) ((float*)r.out)[p] = (float)(s / (double)r.N);
+    else ((float*)r.out)[p] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_one(ReduceArgs r) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= r.n_prog) return;
+    const double* src = r.partials + r.part_base + p;
+    double s = 0.0;
+    for (int32_t t = 0; t < r.blocks; t++) s += src[(int64_t)t * r.stride];
+    if (r.kind == GP_FIT_HITS) ((int32_t*)r.out)[p] = (int32_t)s;
+    else if (r.kind == GP_FIT_MSE) ((float*)r.out)[p] = (float)(s / (double)r.N);
+    else ((float*)r.out)[p] = (float)s;
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+hipError_t core_launch(int vi, const CoreArgs& a, uint32_t blocks, hipStream_t s) {
+    const CoreVariantDesc& v = kCoreVariants[vi];
+#define GPX_LAUNCH(T, D, NF)                                                      \
+    if (v.t == T && v.d == D && v.nf == NF) {                                     \
+        hipLaunchKernelGGL((k_core<T, D, NF>), dim3(blocks), dim3(256), 0, s, a); \
+        return hipGetLastError();                                                 \
+    }
+    GPX_CORE_VARIANTS(GPX_LAUNCH)
+#undef GPX_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+int core_blocks_per_cu(int vi) {
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    int n = 0;
+#define GPX_OCC(T, D, NF)                                                                                 \
+    if (v.t == T && v.d == D && v.nf == NF) {                                                             \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_core<T, D, NF>, 256, 0) != hipSuccess) n = 1; \
+    }
+    GPX_CORE_VARIANTS(GPX_OCC)
+#undef GPX_OCC
+    return n > 0 ? n : 1;
+}
+
+hipError_t core_zero_counter(uint32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t core_reduce_jobs(const ReduceArgs* jobs_dev, int32_t n_jobs, int64_t max_prog, hipStream_t s) {
+    if (n_jobs <= 0 || max_prog <= 0) return hipSuccess;
+    const uint32_t bx = (uint32_t)((max_prog + 255) / 256);
+    hipLaunchKernelGGL(k_reduce_jobs, dim3(bx, (uint32_t)n_jobs), dim3(256), 0, s, jobs_dev);
+    return hipGetLastError();
+}
+
+hipError_t core_reduce_one(const ReduceArgs& r, hipStream_t s) {
+    if (r.n_prog <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_one, dim3((uint32_t)((r.n_prog + 255) / 256)), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
+}  // namespace gpx

@@ -1,0 +1,417 @@
+"""Generate the hand-written gfx950 interpreter core (a build step).
+
+    python gen_core.py OUT_DIR
+
+Writes ``core_gen.inc``: for every kernel variant (T case slots per lane, D
+stack levels, NF feature slots) one inline-asm interpreter loop plus the
+host-side table naming its handlers.
+
+Design.  The whole two-dimensional stack (level l, slot j), the registers of
+a linear program and the wave's case tile live in a VGPR range the compiler
+does not allocate (the kernel caps the compiler's own VGPRs).  Offsets in
+that range, relative to its first register V0:
+
+    stack level l / linear register r, slot j :  l*T + j        (l < RB)
+    feature f, slot j                          :  RB*T + f*T + j  (f < NF)
+
+with RB = max(8, D) register/stack levels.
+
+A program is a list of 16-byte instructions
+
+    dword 0-1  absolute address of the handler that executes it
+    dword 2    operand offsets (byte 0 = first index, byte 1 = second index;
+               for an exit: A, B, destination offsets and the operation)
+    dword 3    constant operand (binary32 bits)
+
+A handler loads the next instruction with one scalar load, executes its own
+T vector instructions with the wave-uniform operand offset applied through
+the gfx9 VGPR index mode (one index per instruction; the other operands of
+the handler are fixed registers, so handlers are specialised on stack level
+or register number), waits for the load and jumps to the next handler's
+address.  Every lane runs the same program, so the jump is uniform.  Work
+the core does not do itself (protected division, sin/cos/exp/log, the end
+of a program) leaves the asm block through the exit handler with the
+instruction's payload; the compiled kernel does it and re-enters.
+
+Fixed SGPRs used by the block: s[60:61] code base, s62 byte offset of the
+current instruction, s63 probe flag, s[64:67] current instruction, s70-s71
+indices, s72 constant, s[76:77] table address (probe).
+"""
+import os
+import sys
+
+SLOT = 64                 # bytes per handler slot; longer handlers take several
+LIN_REGS = 8              # register slots reserved for linear programs (and stack levels)
+NCV = 40                  # VGPRs left to the compiler; the core owns v[NCV ...]
+
+# (T, D, NF) variants.  Tree stack levels D <= 8 share the register slots.
+VARIANTS = [
+    (8, 6, 8),
+    (8, 8, 8),
+    (4, 8, 8),
+    (4, 8, 16),
+    (4, 12, 32),
+]
+
+OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
+OP_ID = {"add": 0, "sub": 1, "mul": 2}
+
+# handler kinds (keep in sync with the generated enum below)
+KINDS = ["EXIT", "SS", "SSR", "SX", "XS", "SC", "CS", "XX", "XX2", "XC", "CX", "PUSHX", "PUSHC",
+         "RR", "XR", "FF", "CR", "RC", "MOVC", "MOVX"]
+K = {k: i for i, k in enumerate(KINDS)}
+
+
+def vr(n):
+    assert 0 <= n < 256, n
+    return "v%d" % n
+
+
+class Handler:
+    def __init__(self, kind, op=0, p1=0, p2=0):
+        self.kind, self.op, self.p1, self.p2 = kind, op, p1, p2
+        self.lines = []
+        self.size = 0
+
+    def emit(self, text, nbytes):
+        self.lines.append(text)
+        self.size += nbytes
+
+
+def gen_variant(T, D, NF):
+    V0 = NCV
+    FO = max(LIN_REGS, D) * T          # register/stack block, then the features
+    assert FO + NF * T <= 256, "index range exceeds 8 bits"
+    assert V0 + FO + NF * T <= 256
+    tag = "T%dD%dF%d" % (T, D, NF)
+    hs = []
+
+    def prologue(h, const=False, second_index=False):
+        if const:
+            h.emit("s_mov_b32 s72, s67", 4)
+        h.emit("s_mov_b32 s70, s66", 4)
+        if second_index:
+            h.emit("s_lshr_b32 s71, s66, 8", 4)
+        h.emit("s_add_u32 s62, s62, 16", 4)
+        h.emit("s_load_dwordx4 s[64:67], s[60:61], s62", 8)
+
+    def idx_on(h, sreg, modes):
+        h.emit("s_set_gpr_idx_on %s, gpr_idx(%s)" % (sreg, ",".join(modes)), 4)
+
+    def epilogue(h):
+        h.emit("s_waitcnt lgkmcnt(0)", 4)
+        h.emit("s_setpc_b64 s[64:65]", 4)
+
+    def valu(h, text):
+        h.emit(text, 4)
+
+    # ---------------------------------------------------------------- exit
+    h = Handler(K["EXIT"])
+    h.emit("s_set_gpr_idx_off", 4)
+    h.emit("s_branch .Lgpx_end_%s" % tag, 4)
+    hs.append(h)
+
+    # ---------------------------------------------------------------- trees
+    for op in ("add", "sub", "mul"):
+        h = Handler(K["SS"], OP_ID[op])            # s[h-2] = s[h-2] op s[h-1]; index (h-2)*T
+        prologue(h)
+        idx_on(h, "s70", ["SRC0", "SRC1", "DST"])
+        for j in range(T):
+            valu(h, "%s %s, %s, %s" % (OPS[op], vr(V0 + j), vr(V0 + j), vr(V0 + T + j)))
+        epilogue(h)
+        hs.append(h)
+    h = Handler(K["SSR"], OP_ID["sub"])            # s[h-2] = s[h-1] - s[h-2]
+    prologue(h)
+    idx_on(h, "s70", ["SRC0", "SRC1", "DST"])
+    for j in range(T):
+        valu(h, "v_sub_f32_e32 %s, %s, %s" % (vr(V0 + j), vr(V0 + T + j), vr(V0 + j)))
+    epilogue(h)
+    hs.append(h)
+    for op in ("add", "sub", "mul"):
+        for l in range(D):
+            h = Handler(K["SX"], OP_ID[op], l)     # s[l] = s[l] op x[b]; index = feature offset
+            prologue(h)
+            idx_on(h, "s70", ["SRC1"])
+            for j in range(T):
+                r = vr(V0 + l * T + j)
+                valu(h, "%s %s, %s, %s" % (OPS[op], r, r, vr(V0 + j)))
+            epilogue(h)
+            hs.append(h)
+    for l in range(D):
+        h = Handler(K["XS"], OP_ID["sub"], l)      # s[l] = x[a] - s[l]
+        prologue(h)
+        idx_on(h, "s70", ["SRC0"])
+        for j in range(T):
+            r = vr(V0 + l * T + j)
+            valu(h, "v_sub_f32_e32 %s, %s, %s" % (r, vr(V0 + j), r))
+        epilogue(h)
+        hs.append(h)
+    for op, ins in (("add", "v_add_f32_e32"), ("mul", "v_mul_f32_e32"), ("sub", "v_subrev_f32_e32")):
+        h = Handler(K["SC"], OP_ID[op])            # s[l] = s[l] op c; index l*T
+        prologue(h, const=True)
+        idx_on(h, "s70", ["SRC1", "DST"])
+        for j in range(T):
+            valu(h, "%s %s, s72, %s" % (ins, vr(V0 + j), vr(V0 + j)))
+        epilogue(h)
+        hs.append(h)
+    h = Handler(K["CS"], OP_ID["sub"])             # s[l] = c - s[l]
+    prologue(h, const=True)
+    idx_on(h, "s70", ["SRC1", "DST"])
+    for j in range(T):
+        valu(h, "v_sub_f32_e32 %s, s72, %s" % (vr(V0 + j), vr(V0 + j)))
+    epilogue(h)
+    hs.append(h)
+    if NF <= 8:
+        # push x[a] op x[b] at level l: both sources relative to one index a*T,
+        # the second one displaced by delta = b - a feature rows
+        for op in ("add", "mul", "sub"):
+            deltas = range(0, NF) if op != "sub" else range(-(NF - 1), NF)
+            for l in range(D):
+                for dl in deltas:
+                    h = Handler(K["XX"], OP_ID[op], l, dl)
+                    prologue(h)
+                    idx_on(h, "s70", ["SRC0", "SRC1"])
+                    for j in range(T):
+                        valu(h, "%s %s, %s, %s" % (OPS[op], vr(V0 + l * T + j), vr(V0 + FO + j),
+                                                   vr(V0 + FO + dl * T + j)))
+                    epilogue(h)
+                    hs.append(h)
+    for op in ("add", "sub", "mul"):
+        for l in range(D):
+            h = Handler(K["XX2"], OP_ID[op], l)    # two passes: s[l] = x[b]; s[l] = x[a] op s[l]
+            prologue(h, second_index=True)
+            idx_on(h, "s71", ["SRC0"])
+            for j in range(T):
+                valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + l * T + j), vr(V0 + j)))
+            idx_on(h, "s70", ["SRC0"])
+            for j in range(T):
+                r = vr(V0 + l * T + j)
+                valu(h, "%s %s, %s, %s" % (OPS[op], r, vr(V0 + j), r))
+            epilogue(h)
+            hs.append(h)
+    for op, ins in (("add", "v_add_f32_e32"), ("mul", "v_mul_f32_e32"), ("sub", "v_subrev_f32_e32")):
+        for l in range(D):
+            h = Handler(K["XC"], OP_ID[op], l)     # push x[a] op c
+            prologue(h, const=True)
+            idx_on(h, "s70", ["SRC1"])
+            for j in range(T):
+                valu(h, "%s %s, s72, %s" % (ins, vr(V0 + l * T + j), vr(V0 + j)))
+            epilogue(h)
+            hs.append(h)
+    for l in range(D):
+        h = Handler(K["CX"], OP_ID["sub"], l)      # push c - x[b]
+        prologue(h, const=True)
+        idx_on(h, "s70", ["SRC1"])
+        for j in range(T):
+            valu(h, "v_sub_f32_e32 %s, s72, %s" % (vr(V0 + l * T + j), vr(V0 + j)))
+        epilogue(h)
+        hs.append(h)
+    h = Handler(K["PUSHX"])                        # s[0] = x[a] (a program that is one variable)
+    prologue(h)
+    idx_on(h, "s70", ["SRC0"])
+    for j in range(T):
+        valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + j), vr(V0 + j)))
+    epilogue(h)
+    hs.append(h)
+    h = Handler(K["PUSHC"])                        # s[l] = c; index l*T
+    prologue(h, const=True)
+    idx_on(h, "s70", ["DST"])
+    for j in range(T):
+        valu(h, "v_mov_b32_e32 %s, s72" % vr(V0 + j))
+    epilogue(h)
+    hs.append(h)
+
+    # ---------------------------------------------------------------- linear
+    R = LIN_REGS
+    for op in ("add", "sub", "mul"):
+        for d in range(R):
+            for s1 in range(R):
+                h = Handler(K["RR"], OP_ID[op], d, s1)   # r[d] = r[s1] op src2 (index)
+                prologue(h)
+                idx_on(h, "s70", ["SRC1"])
+                for j in range(T):
+                    valu(h, "%s %s, %s, %s" % (OPS[op], vr(V0 + d * T + j), vr(V0 + s1 * T + j), vr(V0 + j)))
+                epilogue(h)
+                hs.append(h)
+    for d in range(R):
+        for s2 in range(R):
+            h = Handler(K["XR"], OP_ID["sub"], d, s2)    # r[d] = src1 (index) - r[s2]
+            prologue(h)
+            idx_on(h, "s70", ["SRC0"])
+            for j in range(T):
+                valu(h, "v_sub_f32_e32 %s, %s, %s" % (vr(V0 + d * T + j), vr(V0 + j), vr(V0 + s2 * T + j)))
+            epilogue(h)
+            hs.append(h)
+    for op in ("add", "sub", "mul"):
+        for d in range(R):
+            h = Handler(K["FF"], OP_ID[op], d)           # r[d] = src2; r[d] = src1 op r[d]
+            prologue(h, second_index=True)
+            idx_on(h, "s71", ["SRC0"])
+            for j in range(T):
+                valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + d * T + j), vr(V0 + j)))
+            idx_on(h, "s70", ["SRC0"])
+            for j in range(T):
+                r = vr(V0 + d * T + j)
+                valu(h, "%s %s, %s, %s" % (OPS[op], r, vr(V0 + j), r))
+            epilogue(h)
+            hs.append(h)
+    for op in ("add", "sub", "mul"):
+        for d in range(R):
+            h = Handler(K["CR"], OP_ID[op], d)           # r[d] = c op src (index)
+            prologue(h, const=True)
+            idx_on(h, "s70", ["SRC1"])
+            for j in range(T):
+                valu(h, "%s %s, s72, %s" % (OPS[op], vr(V0 + d * T + j), vr(V0 + j)))
+            epilogue(h)
+            hs.append(h)
+    for d in range(R):
+        h = Handler(K["RC"], OP_ID["sub"], d)            # r[d] = src (index) - c
+        prologue(h, const=True)
+        idx_on(h, "s70", ["SRC1"])
+        for j in range(T):
+            valu(h, "v_subrev_f32_e32 %s, s72, %s" % (vr(V0 + d * T + j), vr(V0 + j)))
+        epilogue(h)
+        hs.append(h)
+    for d in range(R):
+        h = Handler(K["MOVC"], 0, d)                     # r[d] = c
+        prologue(h, const=True)
+        h.emit("s_set_gpr_idx_off", 4)
+        for j in range(T):
+            valu(h, "v_mov_b32_e32 %s, s72" % vr(V0 + d * T + j))
+        epilogue(h)
+        hs.append(h)
+    for d in range(R):
+        h = Handler(K["MOVX"], 0, d)                     # r[d] = src (index)
+        prologue(h)
+        idx_on(h, "s70", ["SRC0"])
+        for j in range(T):
+            valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + d * T + j), vr(V0 + j)))
+        epilogue(h)
+        hs.append(h)
+
+    # ---------------------------------------------------------------- layout
+    slot = 0
+    for h in hs:
+        h.slot = slot
+        slot += (h.size + SLOT - 1) // SLOT
+    return tag, V0, FO, hs, slot
+
+
+def asm_text(T, D, NF, tag, hs):
+    L = []
+    L.append("s_getpc_b64 s[76:77]")
+    L.append(".Lgpx_pc_%s:" % tag)
+    L.append("s_cmp_eq_u32 s63, 0")
+    L.append("s_cbranch_scc1 .Lgpx_run_%s" % tag)
+    L.append("s_add_u32 s76, s76, .Lgpx_table_%s-.Lgpx_pc_%s" % (tag, tag))
+    L.append("s_addc_u32 s77, s77, 0")
+    L.append("s_branch .Lgpx_end_%s" % tag)
+    L.append(".Lgpx_run_%s:" % tag)
+    L.append("s_load_dwordx4 s[64:67], s[60:61], s62")
+    L.append("s_waitcnt lgkmcnt(0)")
+    L.append("s_setpc_b64 s[64:65]")
+    L.append(".p2align %d" % (SLOT.bit_length() - 1))
+    L.append(".Lgpx_table_%s:" % tag)
+    for i, h in enumerate(hs):
+        lab = ".Lgpx_h%d_%s" % (i, tag)
+        L.append("%s:" % lab)
+        # the host addresses handlers by slot: check the slot arithmetic
+        L.append(".if (%s - .Lgpx_table_%s) != %d" % (lab, tag, h.slot * SLOT))
+        L.append('.error \\"gpx handler %d misplaced\\"' % i)
+        L.append(".endif")
+        L.extend(h.lines)
+        # pad to the slot boundary (never executed: every handler ends in a jump)
+        pad = (-h.size) % SLOT
+        L.extend(["s_nop 0"] * (pad // 4))
+    L.append(".Lgpx_end_%s:" % tag)
+    return "\\n\\t".join(L)
+
+
+def gather_scatter(T, V0):
+    """C++ helpers moving T slots between compiler VGPRs and the core's range."""
+    out = []
+    outs = ", ".join('"=v"(v[%d])' % j for j in range(T))
+    movs = "".join("v_mov_b32_e32 %%%d, %s\\n\\t" % (j, vr(V0 + j)) for j in range(T))
+    out.append("template <> __device__ __forceinline__ void core_gather<%d>(uint32_t off, float (&v)[%d]) {" % (T, T))
+    out.append("#ifdef __HIP_DEVICE_COMPILE__")
+    out.append('    asm volatile("s_set_gpr_idx_on %%%d, gpr_idx(SRC0)\\n\\t%ss_set_gpr_idx_off" : %s : "s"(off) : "m0");'
+               % (T, movs, outs))
+    out.append("#endif")
+    out.append("}")
+    ins = ", ".join('"v"(v[%d])' % j for j in range(T))
+    movs = "".join("v_mov_b32_e32 %s, %%%d\\n\\t" % (vr(V0 + j), j + 1) for j in range(T))
+    out.append("template <> __device__ __forceinline__ void core_scatter<%d>(uint32_t off, const float (&v)[%d]) {"
+               % (T, T))
+    out.append("#ifdef __HIP_DEVICE_COMPILE__")
+    out.append('    asm volatile("s_set_gpr_idx_on %%0, gpr_idx(DST)\\n\\t%ss_set_gpr_idx_off" : : "s"(off), %s : "m0");'
+               % (movs, ins))
+    out.append("#endif")
+    out.append("}")
+    return "\n".join(out)
+
+
+def main(out_dir):
+    os.makedirs(out_dir, exist_ok=True)
+    lines = ["// Generated by gen_core.py -- do not edit.", "#pragma once", ""]
+    lines.append("#define GPX_NCV %d" % NCV)
+    # amdgpu_num_vgpr(n) lets the compiler allocate 2n VGPRs on gfx950
+    # (checked at build time against the compiler's reserved-register report)
+    lines.append("#define GPX_NUM_VGPR_ATTR %d" % (NCV // 2))
+    lines.append("#define GPX_CORE_VGPR_END %d" % max(NCV + max(LIN_REGS, d) * t + nf * t for (t, d, nf) in VARIANTS))
+    lines.append("#define GPX_LIN_REGS %d" % LIN_REGS)
+    lines.append("#define GPX_SLOT %d" % SLOT)
+    lines.append("enum CoreKind {" + ", ".join("CK_%s = %d" % (k, i) for i, k in enumerate(KINDS)) + "};")
+    lines.append("")
+    lines.append("#define GPX_CORE_VARIANTS(X) \\")
+    lines.append(" \\\n".join("    X(%d, %d, %d)" % v for v in VARIANTS))
+    lines.append("")
+    clob_s = ", ".join('"s%d"' % n for n in (63, 64, 65, 66, 67, 70, 71, 72, 76, 77))
+    lines.append("template <int T, int D, int NF> struct Core;")
+    lines.append("template <int T> __device__ void core_gather(uint32_t off, float (&v)[T]);")
+    lines.append("template <int T> __device__ void core_scatter(uint32_t off, const float (&v)[T]);")
+    for T in sorted(set(v[0] for v in VARIANTS)):
+        lines.append(gather_scatter(T, NCV))
+    host = []
+    for (T, D, NF) in VARIANTS:
+        tag, V0, FO, hs, nslots = gen_variant(T, D, NF)
+        text = asm_text(T, D, NF, tag, hs)
+        clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
+        assert NCV + FO + NF * T <= 256
+        lines.append("template <> struct Core<%d, %d, %d> {" % (T, D, NF))
+        lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")
+        lines.append("    static __device__ __forceinline__ void run(uint64_t base, uint32_t& off, uint32_t& pay,"
+                     " uint32_t& cst, uint32_t probe, uint64_t& table) {")
+        lines.append("#ifdef __HIP_DEVICE_COMPILE__")
+        lines.append('        asm volatile("%s"' % text)
+        lines.append('            : "+{s62}"(off), "={s66}"(pay), "={s67}"(cst), "={s[76:77]}"(table)')
+        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe)')
+        lines.append('            : %s, "s64", "s65", "s70", "s71", "s72", "scc", "m0", "memory");' % clob_v)
+        lines.append("#endif")
+        lines.append("    }")
+        lines.append("};")
+        host.append((T, D, NF, tag, hs, nslots))
+    lines.append("")
+    lines.append("struct CoreHandlerKey { uint8_t kind, op; int8_t p1, p2; };")
+    for (T, D, NF, tag, hs, nslots) in host:
+        lines.append("static const CoreHandlerKey kCoreKeys_%s[] = {" % tag)
+        lines.append("    " + ", ".join("{%d,%d,%d,%d}" % (h.kind, h.op, h.p1, h.p2) for h in hs))
+        lines.append("};")
+        lines.append("static const uint16_t kCoreSlots_%s[] = {" % tag)
+        lines.append("    " + ", ".join(str(h.slot) for h in hs))
+        lines.append("};")
+    lines.append("struct CoreVariantDesc { int t, d, nf; const CoreHandlerKey* keys; const uint16_t* slots; int n; int table_bytes; };")
+    lines.append("static const CoreVariantDesc kCoreVariants[] = {")
+    for (T, D, NF, tag, hs, nslots) in host:
+        lines.append("    {%d, %d, %d, kCoreKeys_%s, kCoreSlots_%s, %d, %d}," % (T, D, NF, tag, tag, len(hs), nslots * SLOT))
+    lines.append("};")
+    path = os.path.join(out_dir, "core_gen.inc")
+    with open(path + ".tmp", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    os.replace(path + ".tmp", path)
+    for (T, D, NF, tag, hs, nslots) in host:
+        print("%s: %d handlers, %d slots (%d KiB)" % (tag, len(hs), nslots, nslots * SLOT // 1024))
+    return path
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else ".")

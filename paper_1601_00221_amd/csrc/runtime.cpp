@@ -15,8 +15,9 @@
 #include <vector>
 
 #include "../../include/gp.h"
+#include "core_host.h"
+#include "core_kernels.h"
 #include "gp_internal.h"
-#include "kernels.h"
 #include "runtime.h"
 
 namespace gpx {
@@ -274,15 +275,20 @@ static void make_groups(const ProgData& pd, int32_t G, std::vector<uint32_t>& or
     }
 }
 
-gp_status upload_programs(const ProgData& pd, DevProgs& dp, hipStream_t s, Workspace& w) {
-    gp_status st;
-    if ((st = dp.code.reserve(std::max<size_t>(4, pd.code.size() * 4))) != GP_OK) return st;
-    if ((st = dp.progs.reserve(std::max<size_t>(1, pd.progs.size()) * sizeof(DevProg))) != GP_OK) return st;
-    if ((st = w.staging.begin(pd.code.size() * 4 + pd.progs.size() * sizeof(DevProg) + 1024)) != GP_OK) return st;
-    if ((st = w.staging.put(pd.code.data(), pd.code.size() * 4, dp.code.p, s)) != GP_OK) return st;
-    if ((st = w.staging.put(pd.progs.data(), pd.progs.size() * sizeof(DevProg), dp.progs.p, s)) != GP_OK) return st;
+static gp_status upload_core(const ProgData& pd, int vi, DevProgs& dp, hipStream_t s, Workspace& w) {
+    std::vector<uint32_t> code;
+    std::vector<DevProg> progs;
+    gp_status st = core_translate(pd, vi, code, progs);
+    if (st != GP_OK) return st;
+    if ((st = dp.code.reserve(std::max<size_t>(16, code.size() * 4))) != GP_OK) return st;
+    if ((st = dp.progs.reserve(std::max<size_t>(1, progs.size()) * sizeof(DevProg))) != GP_OK) return st;
+    if ((st = w.staging.begin(code.size() * 4 + progs.size() * sizeof(DevProg) + 1024)) != GP_OK) return st;
+    if ((st = w.staging.put(code.data(), code.size() * 4, dp.code.p, s)) != GP_OK) return st;
+    if ((st = w.staging.put(progs.data(), progs.size() * sizeof(DevProg), dp.progs.p, s)) != GP_OK) return st;
+    if ((st = w.staging.end(s)) != GP_OK) return st;
     dp.groups_by_G.clear();
-    return w.staging.end(s);
+    dp.uploaded = true;
+    return GP_OK;
 }
 
 static gp_status groups_for(const ProgData& pd, DevProgs& dp, int32_t G, hipStream_t s, Workspace& w,
@@ -349,8 +355,8 @@ hipError_t timed_launch_end(hipStream_t s, int slot) {
     return hipEventRecord(g_tm_events[slot].second, s);
 }
 
-gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_feat, int64_t N,
-                    const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
+gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
+                    int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
                     const EvalOptions* opt) {
     if (!X) return fail(GP_E_INVAL, "X is null");
     if (!out) return fail(GP_E_INVAL, "out is null");
@@ -361,25 +367,31 @@ gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_
     if (pd.n_prog == 0) return GP_OK;
     if (pd.n_load > GP_MAX_FEAT)
         return fail(GP_E_INVAL, "programs read feature %d; at most %d features are supported", pd.n_load - 1, GP_MAX_FEAT);
-    int vi = opt && opt->variant >= 0 ? opt->variant : pick_variant(pd.n_load, pd.max_depth);
-    if (vi < 0 || vi >= n_variants()) return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
-    const VariantDesc& v = variant(vi);
-    if (v.fv < pd.n_load || v.d < pd.max_depth) return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
-    const int64_t tiles64 = (N + 64LL * v.t - 1) / (64LL * v.t);
+    const int vi = opt && opt->variant >= 0 ? opt->variant : pick_core_variant(pd.n_load, pd.max_depth);
+    if (vi < 0 || vi >= core_variants())
+        return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
+    if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth)
+        return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
+    gp_status st;
+    if ((st = core_ready(vi, s)) != GP_OK) return st;
+    DevProgs& dp = dps[vi];
+    if (fresh || !dp.uploaded)
+        if ((st = upload_core(pd, vi, dp, s, w)) != GP_OK) return st;
+    const int T = core_variant_t(vi);
+    const int64_t tiles64 = (N + 64LL * T - 1) / (64LL * T);
     if (tiles64 > (1LL << 30)) return fail(GP_E_INVAL, "n_cases too large");
     const int32_t tiles = (int32_t)tiles64;
     const int32_t target = opt && opt->target_units > 0 ? opt->target_units : 16384;
     const int32_t G = opt && opt->groups > 0 ? std::min(opt->groups, pd.n_prog) : choose_groups(pd.n_prog, tiles, target);
     const int64_t units = (int64_t)tiles * G;
     if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
-    gp_status st;
     const uint32_t *order, *goff;
     if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
     const int64_t n_blocks = (N + 255) / 256;
     if (kind != GP_OUT_CASES) {
         if ((st = w.partials.reserve((size_t)n_blocks * pd.n_prog * sizeof(double))) != GP_OK) return st;
     }
-    EvalArgs a;
+    CoreArgs a;
     memset(&a, 0, sizeof a);
     a.code = (const uint32_t*)dp.code.p;
     a.progs = (const DevProg*)dp.progs.p;
@@ -387,17 +399,18 @@ gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_
     a.group_off = goff;
     a.X = X;
     a.y = kind == GP_OUT_CASES ? nullptr : y;
-    a.partials = (double*)w.partials.p;
-    a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
     a.N = N;
     a.n_load = pd.n_load;
-    a.n_feat_prog = pd.n_feat;
+    a.kind = kind;
     a.tiles = tiles;
     a.n_units = (int32_t)units;
-    a.kind = kind;
+    a.partials = (double*)w.partials.p;
+    a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
+    uint32_t blocks = (uint32_t)((units + 3) / 4);
+    blocks = (blocks + 7u) & ~7u;
     int slot;
     hipError_t e = timed_launch_begin(s, &slot);
-    if (e == hipSuccess) e = launch_eval(vi, a, s);
+    if (e == hipSuccess) e = core_launch(vi, a, blocks, s);
     if (e == hipSuccess) e = timed_launch_end(s, slot);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "evaluation launch: %s", hipGetErrorString(e));
     if (kind == GP_OUT_CASES) return GP_OK;
@@ -411,7 +424,7 @@ gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_
     r.out = out;
     r.blocks = (int32_t)n_blocks;
     r.kind = kind;
-    e = launch_reduce(r, s);
+    e = core_reduce_one(r, s);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "reduction launch: %s", hipGetErrorString(e));
     return GP_OK;
 }
@@ -425,7 +438,7 @@ using namespace gpx;
 
 struct gp_progset {
     ProgData pd;
-    DevProgs dp;
+    std::map<int, DevProgs> dps;   // translated per core variant, uploaded on first use
     std::mutex mu;
 };
 
@@ -445,8 +458,7 @@ gp_status gp_eval_tree(const int32_t* tok, const float* cst, const int64_t* off,
     hipStream_t s = (hipStream_t)stream;
     Workspace& w = workspace(s);
     std::lock_guard<std::mutex> g(w.mu);
-    if ((st = upload_programs(pd, w.oneshot, s, w)) != GP_OK) return st;
-    return eval_core(pd, w.oneshot, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+    return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
 }
 
 gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
@@ -459,20 +471,13 @@ gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* 
     hipStream_t s = (hipStream_t)stream;
     Workspace& w = workspace(s);
     std::lock_guard<std::mutex> g(w.mu);
-    if ((st = upload_programs(pd, w.oneshot, s, w)) != GP_OK) return st;
-    return eval_core(pd, w.oneshot, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+    return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
 }
 
 static gp_status progset_finish(ProgData&& pd, void* stream, gp_progset** ps) {
+    (void)stream;   // programs are translated and uploaded on first evaluation, per kernel variant
     std::unique_ptr<gp_progset> p(new gp_progset());
     p->pd = std::move(pd);
-    hipStream_t s = (hipStream_t)stream;
-    if (p->pd.n_prog > 0) {
-        Workspace& w = workspace(s);
-        std::lock_guard<std::mutex> g(w.mu);
-        gp_status st = upload_programs(p->pd, p->dp, s, w);
-        if (st != GP_OK) return st;
-    }
     *ps = p.release();
     return GP_OK;
 }
@@ -506,7 +511,7 @@ gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_
     Workspace& w = workspace(s);
     std::lock_guard<std::mutex> g(w.mu);
     std::lock_guard<std::mutex> g2(ps->mu);
-    return eval_core(ps->pd, ps->dp, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+    return eval_core(ps->pd, ps->dps, false, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
 }
 
 gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
@@ -524,9 +529,47 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
 gp_status gp_progset_destroy(gp_progset* ps) {
     clear_error();
     if (!ps) return GP_OK;
-    ps->dp.release();
+    for (auto& kv : ps->dps) kv.second.release();
     delete ps;
     return GP_OK;
+}
+
+static gp_status core_lower_common(ProgData& pd, int32_t variant, uint64_t table_base, uint32_t* words,
+                                   int64_t max_words, int64_t* prog_off, int64_t* n_words) {
+    std::vector<uint32_t> code;
+    std::vector<DevProg> progs;
+    gp_status st = core_translate_at(pd, variant, table_base, code, progs);
+    if (st != GP_OK) return st;
+    if (n_words) *n_words = (int64_t)code.size();
+    if (words) {
+        if (max_words < (int64_t)code.size()) return fail(GP_E_INVAL, "words buffer too small");
+        memcpy(words, code.data(), code.size() * 4);
+    }
+    if (prog_off) {
+        for (int32_t p = 0; p < pd.n_prog; p++) prog_off[p] = progs[p].code_off;
+        prog_off[pd.n_prog] = (int64_t)code.size();
+    }
+    return GP_OK;
+}
+
+gp_status gp_core_lower_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog, int32_t n_feat,
+                             int32_t variant, uint64_t table_base, uint32_t* words, int64_t max_words,
+                             int64_t* prog_off, int64_t* n_words) {
+    clear_error();
+    ProgData pd;
+    gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd);
+    if (st != GP_OK) return st;
+    return core_lower_common(pd, variant, table_base, words, max_words, prog_off, n_words);
+}
+
+gp_status gp_core_lower_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
+                               int32_t n_prog, int32_t n_reg, int32_t n_feat, int32_t variant, uint64_t table_base,
+                               uint32_t* words, int64_t max_words, int64_t* prog_off, int64_t* n_words) {
+    clear_error();
+    ProgData pd;
+    gp_status st = build_linear(code, off, cst, cst_off, n_prog, n_reg, n_feat, pd);
+    if (st != GP_OK) return st;
+    return core_lower_common(pd, variant, table_base, words, max_words, prog_off, n_words);
 }
 
 gp_status gp_timing_enable(int on) {

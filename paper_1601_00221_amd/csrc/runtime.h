@@ -56,12 +56,15 @@ struct ProgData {
     std::vector<uint32_t> cost;
 };
 
-// Device copies of lowered programs plus cached group layouts.
+// Device copies of programs translated for one core variant, plus cached
+// group layouts.
 struct DevProgs {
+    bool uploaded = false;
     DevBuf code;
     DevBuf progs;
     std::map<int32_t, std::pair<int64_t, std::unique_ptr<DevBuf>>> groups_by_G;
     void release() {
+        uploaded = false;
         code.release();
         progs.release();
         for (auto& kv : groups_by_G) kv.second.second->release();
@@ -74,11 +77,11 @@ struct Workspace {
     std::mutex mu;
     DevBuf partials;
     Staging staging;
-    DevProgs oneshot;
+    std::map<int, DevProgs> oneshot;   // by core variant
 };
 
 struct EvalOptions {
-    int variant = -1;        // kernel variant index, -1 = pick by footprint
+    int variant = -1;        // core variant index, -1 = widest tile that fits
     int32_t groups = 0;      // program groups, 0 = automatic
     int32_t target_units = 0;
 };
@@ -93,8 +96,10 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
                      ProgData& pd);
 gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
                        int32_t P, int32_t n_reg, int32_t n_feat, ProgData& pd);
-gp_status upload_programs(const ProgData& pd, DevProgs& dp, hipStream_t s, Workspace& w);
-gp_status eval_core(const ProgData& pd, DevProgs& dp, const float* X, int32_t n_feat, int64_t N, const float* y,
-                    int32_t kind, void* out, hipStream_t s, Workspace& w, const EvalOptions* opt);
+// Evaluate lowered programs on one case matrix.  dps caches the programs
+// translated per core variant; fresh forces a new translation and upload.
+gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
+                    int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
+                    const EvalOptions* opt);
 
 }  // namespace gpx

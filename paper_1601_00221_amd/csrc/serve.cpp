@@ -22,6 +22,7 @@
 
 #include "../../include/gp.h"
 #include "batch.h"
+#include "core_host.h"
 #include "runtime.h"
 
 namespace gpx {
@@ -132,10 +133,12 @@ static gp_status launch_batch_locked(Server& S, int k, std::vector<std::shared_p
     }
     gp_batch_config c = default_config(refs);
     if (c.variant < 0) return fail(GP_E_DEPTH, "no kernel variant can hold the batch");
-    BatchPlan plan;
-    gp_status st = plan_batch(refs, S.datasets, c, plan);
-    if (st != GP_OK) return st;
     hipStream_t s = S.streams[k];
+    gp_status st = core_ready(c.variant, s);
+    if (st != GP_OK) return st;
+    BatchPlan plan;
+    st = plan_batch(refs, S.datasets, c, plan);
+    if (st != GP_OK) return st;
     BatchScratch& sc = *S.scratch[k];
     std::lock_guard<std::mutex> g(sc.mu);
     if ((st = upload_plan(plan, sc, s)) != GP_OK) return st;

@@ -1,0 +1,253 @@
+"""The hand-written interpreter core, executed on the CPU.
+
+The generated handler code (the same instruction text the kernel assembles)
+is run by a small emulator of the instructions it uses: scalar moves, adds
+and shifts, the scalar load of the next instruction, the jump to its
+handler's address, the VGPR index mode and the FP32 vector operations.
+Programs are translated by the library (gp_core_lower_*), with the handler
+table placed at a chosen address; the work the kernel does outside the core
+(feature loading, protected division and transcendental exits, reading the
+result) is mirrored here.  Outputs must equal the oracle's bit for bit.
+
+This checks the slot arithmetic, every handler's operand offsets and the
+host translation before any of it runs on a GPU."""
+import math
+import os
+import re
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1601_00221_amd as gp
+import synth
+
+CSRC = os.path.join(os.path.dirname(gp.__file__), "csrc")
+sys.path.insert(0, CSRC)
+import gen_core  # noqa: E402
+
+sys.path.pop(0)
+
+BASE = 0x7F12345600C0 & ~63
+
+
+def f32(x):
+    return np.float32(x)
+
+
+class CoreEmu:
+    def __init__(self, variant_index):
+        T, D, NF = gen_core.VARIANTS[variant_index]
+        tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF)
+        self.T, self.D, self.NF, self.V0, self.FO = T, D, NF, V0, FO
+        self.by_slot = {h.slot: h for h in hs}
+        self.prog = {h.slot: [self._parse(x) for x in h.lines] for h in hs}
+        self.v = np.zeros((256, 64), np.float32)
+        self.s = [0] * 128
+        self.steps = 0
+
+    # ------------------------------------------------------------------ parse
+    @staticmethod
+    def _reg(tok):
+        tok = tok.strip()
+        if tok.startswith("v"):
+            return ("v", int(tok[1:]))
+        if tok.startswith("s"):
+            return ("s", int(tok[1:]))
+        return ("i", int(tok, 0))
+
+    def _parse(self, line):
+        m = re.match(r"(\S+)\s*(.*)", line)
+        op, rest = m.group(1), m.group(2)
+        if op == "s_set_gpr_idx_on":
+            r, modes = re.match(r"(s\d+), gpr_idx\(([A-Z0-9,]*)\)", rest).groups()
+            return (op, int(r[1:]), set(modes.split(",")))
+        if op in ("s_set_gpr_idx_off", "s_waitcnt", "s_nop"):
+            return (op,)
+        if op == "s_load_dwordx4":
+            assert rest == "s[64:67], s[60:61], s62", rest
+            return (op,)
+        if op == "s_setpc_b64":
+            assert rest == "s[64:65]"
+            return (op,)
+        if op == "s_branch":
+            assert ".Lgpx_end_" in rest
+            return (op,)
+        args = [self._reg(a) for a in rest.split(",")]
+        return (op, args)
+
+    # ------------------------------------------------------------------ run
+    def run(self, code, off):
+        """Run from byte offset `off` until the exit handler; returns
+        (offset, payload, constant) as the asm block hands them back."""
+        s = self.s
+        s[62] = off
+        w = code[off // 4: off // 4 + 4]
+        s[64], s[65], s[66], s[67] = (int(x) for x in w)
+        idx_on, m0, modes = False, 0, set()
+        while True:
+            addr = s[64] | (s[65] << 32)
+            rel = addr - BASE
+            assert rel >= 0 and rel % gen_core.SLOT == 0, hex(addr)
+            slot = rel // gen_core.SLOT
+            assert slot in self.prog, slot
+            for ins in self.prog[slot]:
+                self.steps += 1
+                op = ins[0]
+                if op == "s_set_gpr_idx_on":
+                    idx_on, m0, modes = True, s[ins[1]] & 255, ins[2]
+                elif op == "s_set_gpr_idx_off":
+                    idx_on = False
+                elif op in ("s_waitcnt", "s_nop"):
+                    pass
+                elif op == "s_load_dwordx4":
+                    o = s[62] // 4
+                    s[64], s[65], s[66], s[67] = (int(x) for x in code[o:o + 4])
+                elif op == "s_setpc_b64":
+                    break
+                elif op == "s_branch":
+                    return s[62], s[66], s[67]
+                elif op == "s_mov_b32":
+                    (_, d), (k, a) = ins[1]
+                    s[d] = s[a] if k == "s" else a
+                elif op == "s_add_u32":
+                    (_, d), (_, a), (_, b) = ins[1]
+                    s[d] = (s[a] + b) & 0xFFFFFFFF
+                elif op == "s_lshr_b32":
+                    (_, d), (_, a), (_, b) = ins[1]
+                    s[d] = s[a] >> b
+                else:
+                    self._valu(op, ins[1], idx_on, m0, modes)
+            else:
+                raise AssertionError("handler fell through")
+
+    def _valu(self, op, args, idx_on, m0, modes):
+        def src(k, a, field):
+            if k == "s":
+                return np.full(64, np.frombuffer(np.uint32(self.s[a]).tobytes(), np.float32)[0])
+            r = a + (m0 if idx_on and field in modes else 0)
+            assert 0 <= r < 256
+            return self.v[r]
+        (_, d) = args[0]
+        dr = d + (m0 if idx_on and "DST" in modes else 0)
+        assert self.V0 <= dr < 256, dr
+        if op == "v_mov_b32_e32":
+            self.v[dr] = src(*args[1], "SRC0")
+            return
+        a = src(*args[1], "SRC0")
+        b = src(*args[2], "SRC1")
+        with np.errstate(all="ignore"):
+            if op == "v_add_f32_e32": r = a + b
+            elif op == "v_sub_f32_e32": r = a - b
+            elif op == "v_subrev_f32_e32": r = b - a
+            elif op == "v_mul_f32_e32": r = a * b
+            else: raise AssertionError(op)
+        self.v[dr] = r.astype(np.float32)
+
+    # ------------------------------------------------------------------ kernel side
+    def gather(self, off):
+        return self.v[self.V0 + off: self.V0 + off + self.T].copy()
+
+    def scatter(self, off, vals):
+        self.v[self.V0 + off: self.V0 + off + self.T] = vals
+
+    def do_exit(self, pay, cst):
+        oa, ob, od = pay & 255, (pay >> 8) & 255, (pay >> 16) & 255
+        op, fl = (pay >> 24) & 15, pay >> 28
+        c = np.frombuffer(np.uint32(cst).tobytes(), np.float32)[0]
+        A = np.full((self.T, 64), c, np.float32) if fl & 1 else self.gather(oa)
+        if op == synth.PDIV:
+            B = np.full((self.T, 64), c, np.float32) if fl & 2 else self.gather(ob)
+            with np.errstate(all="ignore"):
+                R = np.where(np.abs(B) < f32(1e-6), f32(1.0), (A / B).astype(np.float32))
+        else:
+            R = np.vectorize(lambda x: oracle.apply(op, x), otypes=[np.float32])(A)
+        self.scatter(od, R.astype(np.float32))
+
+    def evaluate(self, words, prog_off, X, n_load):
+        T = self.T
+        F, N = X.shape
+        P = len(prog_off) - 1
+        out = np.zeros((P, N), np.float32)
+        lane = np.arange(64)
+        for tile in range((N + 64 * T - 1) // (64 * T)):
+            t0 = tile * 64 * T
+            for f in range(n_load):
+                vals = np.zeros((T, 64), np.float32)
+                for j in range(T):
+                    c = t0 + 64 * j + lane
+                    ok = c < N
+                    vals[j, ok] = X[f, c[ok]]
+                self.scatter(self.FO + f * T, vals)
+            for p in range(P):
+                off = int(prog_off[p]) * 4
+                while True:
+                    off, pay, cst = self.run(words, off)
+                    if (pay >> 24) & 15 == 15:
+                        break
+                    self.do_exit(pay, cst)
+                    off += 16
+                o = self.gather(0)
+                for j in range(T):
+                    c = t0 + 64 * j + lane
+                    ok = c < N
+                    out[p, c[ok]] = o[j, ok]
+        return out
+
+
+def _same(a, b):
+    return (a.view(np.int32) == b.view(np.int32)) | (np.isnan(a) & np.isnan(b))
+
+
+@pytest.mark.parametrize("vi", range(len(gen_core.VARIANTS)))
+def test_core_trees_match_oracle(vi):
+    T, D, NF = gen_core.VARIANTS[vi]
+    F = min(NF, 9)
+    rng = synth.rng_for(300 + vi)
+    pop = synth.ptc2_population(rng, 30, synth.FULL, F, 1, 90, 0.25)
+    pop2 = synth.ramped_half_and_half(rng, 20, synth.ARITH3, F, 2, 5, 64, 0.2)
+    pop3 = synth.trees_from_lists([
+        (np.array([synth.var_tok(F - 1)], np.int32), np.zeros(1, np.float32)),      # lone variable
+        (np.array([synth.CONST], np.int32), np.array([1.25], np.float32)),          # lone constant
+        (np.array([synth.SUB, synth.CONST, synth.CONST], np.int32), np.array([0, 2, 0.5], np.float32)),
+    ])
+    pops = [pop, pop2, pop3]
+    X = synth.uniform_cases(rng, F, 64 * T + 37, -3, 3)
+    emu = CoreEmu(vi)
+    for pp in pops:
+        words, prog_off = gp.core_lower(pp, F, vi, BASE)
+        n_load = F
+        got = emu.evaluate(words, prog_off, X, n_load)
+        ref = oracle.tree_outputs(pp.tok, pp.cst, pp.off, X)
+        assert _same(got, ref).all()
+
+
+@pytest.mark.parametrize("vi", range(len(gen_core.VARIANTS)))
+def test_core_linear_match_oracle(vi):
+    T, D, NF = gen_core.VARIANTS[vi]
+    F = min(NF, 12)
+    rng = synth.rng_for(400 + vi)
+    pop = synth.linear_population(rng, 25, 1, 60, synth.FULL, 8, F, n_const=3)
+    pop_b = synth.linear_population(rng, 10, 1, 40, synth.BASIC, 5, F, n_const=2)
+    X = synth.uniform_cases(rng, F, 64 * T + 5, -3, 3)
+    emu = CoreEmu(vi)
+    for pp in (pop, pop_b):
+        words, prog_off = gp.core_lower(pp, F, vi, BASE)
+        got = emu.evaluate(words, prog_off, X, F)
+        ref = oracle.linear_outputs(pp.code, pp.off, pp.cst, pp.cst_off, pp.n_reg, X)
+        assert _same(got, ref).all()
+
+
+def test_every_handler_is_reachable_and_in_its_slot():
+    for vi, (T, D, NF) in enumerate(gen_core.VARIANTS):
+        tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF)
+        slots = [h.slot for h in hs]
+        assert slots == sorted(slots) and len(set(slots)) == len(slots)
+        for h in hs:
+            assert h.size <= gen_core.SLOT * ((h.size + gen_core.SLOT - 1) // gen_core.SLOT)
+            if h.kind != gen_core.K["EXIT"]:
+                assert h.lines[-1] == "s_setpc_b64 s[64:65]"
+                # the next instruction is loaded before any index-mode vector op reads s[64:67]
+                assert any(x.startswith("s_load_dwordx4") for x in h.lines)
+        assert V0 + FO + NF * T <= 256
