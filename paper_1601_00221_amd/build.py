@@ -46,18 +46,19 @@ def _check_reserved(src: str):
     finally:
         sys.path.pop(0)
     flags = [f for f in FLAGS if f != "-Wno-inline-asm"]
-    cmd = [HIPCC, *flags, "-I", GEN, "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", os.devnull]
+    cmd = [HIPCC, *flags, "-I", GEN, "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o",
+           os.path.join(BUILD, os.path.splitext(src)[0] + "-gfx950.s")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))
     reserved = set()
     for m in re.finditer(r"clobber list contains reserved registers: ([^\[]*)", r.stderr):
         reserved.update(x.strip() for x in m.group(1).split(","))
-    for t, d, nf in gen_core.VARIANTS:
-        end = gen_core.NCV + max(gen_core.LIN_REGS, d) * t + nf * t
-        missing = [n for n in range(gen_core.NCV, end) if "v%d" % n not in reserved]
+    for t, d, nf, ncv in gen_core.VARIANTS:
+        end = ncv + max(gen_core.LIN_REGS, d) * t + nf * t
+        missing = [n for n in range(ncv, end) if "v%d" % n not in reserved]
         if missing:
-            raise RuntimeError("the compiler may allocate core VGPRs %s (variant %s)" % (missing[:8], (t, d, nf)))
+            raise RuntimeError("the compiler may allocate core VGPRs %s (variant %s)" % (missing[:8], (t, d, nf, ncv)))
 
 
 def _compile(src: str) -> str:

@@ -34,15 +34,13 @@ static int device_cus() {
     return cus;
 }
 
-// Smallest compiled variant with tile width t able to hold the batch.
-static int variant_for_t(int t, int n_load, int depth) {
-    int best = -1;
-    for (int i = 0; i < core_variants(); i++) {
-        if (core_variant_t(i) != t || core_variant_nf(i) < n_load || core_variant_d(i) < depth) continue;
-        const int key = core_variant_d(i) * 1000 + core_variant_nf(i);
-        if (best < 0 || key < core_variant_d(best) * 1000 + core_variant_nf(best)) best = i;
+static double exit_fraction(const std::vector<BatchJobRef>& jobs) {
+    int64_t e = 0, n = 0;
+    for (const BatchJobRef& j : jobs) {
+        e += j.pd->n_exit;
+        n += j.pd->n_instr;
     }
-    return best;
+    return n ? (double)e / (double)n : 0.0;
 }
 
 gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_dataset>& ds,
@@ -331,18 +329,13 @@ gp_status tune_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
         n_load = std::max(n_load, j.pd->n_load);
         depth = std::max(depth, j.pd->max_depth);
     }
-    std::vector<int> widths;
-    for (int i = 0; i < core_variants(); i++)
-        if (std::find(widths.begin(), widths.end(), core_variant_t(i)) == widths.end())
-            widths.push_back(core_variant_t(i));
     double best_t = 1e300;
     gp_batch_config b;
     memset(&b, 0, sizeof b);
     b.variant = -1;
     const int unit_sizes[] = {8, 32, 128};
-    for (int t : widths) {
-        const int vi = variant_for_t(t, n_load, depth);
-        if (vi < 0) continue;
+    for (int vi = 0; vi < core_variants(); vi++) {
+        if (core_variant_nf(vi) < n_load || core_variant_d(vi) < depth) continue;
         for (int us : unit_sizes) {
             for (int pers = 1; pers >= 0; pers--) {
                 gp_batch_config c;
@@ -387,7 +380,7 @@ gp_batch_config default_config(const std::vector<BatchJobRef>& jobs) {
     }
     gp_batch_config c;
     memset(&c, 0, sizeof c);
-    c.variant = pick_core_variant(n_load, depth);
+    c.variant = pick_core_variant(n_load, depth, exit_fraction(jobs));
     c.unit_programs = 32;
     c.persistent = 1;
     return c;

@@ -41,15 +41,21 @@ const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
 int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
 int core_reg_levels(int vi) { return kCoreVariants[vi].d > GPX_LIN_REGS ? kCoreVariants[vi].d : GPX_LIN_REGS; }
 
-int pick_core_variant(int n_load, int depth) {
-    // widest tile first; among those the fewest handlers (least code)
+int pick_core_variant(int n_load, int depth, double exit_frac) {
+    // Programs where many instructions leave the core (binary64 transcendentals,
+    // protected division) want room for the compiled code that does that work;
+    // arithmetic programs want more waves.  Then the widest tile, then the
+    // fewest handlers (least code).
+    const bool heavy = exit_frac > 0.2;
     int best = -1;
+    auto score = [&](const CoreVariantDesc& v) {
+        const int fit = heavy ? (v.ncv >= 96) : (v.ncv <= 64);
+        return fit * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
+    };
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
         if (v.nf < n_load || v.d < depth) continue;
-        if (best < 0) { best = i; continue; }
-        const CoreVariantDesc& b = kCoreVariants[best];
-        if (v.t > b.t || (v.t == b.t && (v.nf < b.nf || (v.nf == b.nf && v.n < b.n)))) best = i;
+        if (best < 0 || score(v) > score(kCoreVariants[best])) best = i;
     }
     return best;
 }
@@ -306,6 +312,7 @@ gp_status core_translate_at(const ProgData& pd, int vi, uint64_t base, std::vect
 }
 
 int core_variant_t(int vi) { return kCoreVariants[vi].t; }
+int core_variant_ncv(int vi) { return kCoreVariants[vi].ncv; }
 int core_variant_d(int vi) { return kCoreVariants[vi].d; }
 int core_variant_nf(int vi) { return kCoreVariants[vi].nf; }
 

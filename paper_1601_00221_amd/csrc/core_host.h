@@ -16,9 +16,11 @@ int core_variants();
 int core_variant_t(int vi);        // case slots per lane
 int core_variant_d(int vi);        // stack levels
 int core_variant_nf(int vi);       // feature slots
+int core_variant_ncv(int vi);      // VGPRs left to the compiled code
 int core_reg_levels(int vi);       // register/stack levels before the features
-// Widest-tile variant able to hold n_load features and `depth` levels, or -1.
-int pick_core_variant(int n_load, int depth);
+// Variant for programs reading n_load features, needing `depth` stack levels,
+// with a fraction exit_frac of instructions leaving the core; -1 if none fits.
+int pick_core_variant(int n_load, int depth, double exit_frac);
 // Locate the variant's handler table on the current device (one probe launch
 // on stream s the first time).
 gp_status core_ready(int vi, hipStream_t s);

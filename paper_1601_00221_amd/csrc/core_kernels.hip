@@ -51,7 +51,7 @@ __device__ __forceinline__ float plog(float a) {
 // Exit payload: byte 0 offset of A, byte 1 offset of B, byte 2 offset of the
 // destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
 // the constant, bit 5: B is the constant).
-template <int T>
+template <int T, int V0>
 __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
     const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
     const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
@@ -62,17 +62,17 @@ __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
 #pragma unroll
             for (int j = 0; j < T; j++) A[j] = c;
         } else {
-            core_gather<T>(oa, A);
+            core_gather<T, V0>(oa, A);
         }
         if (fl & 2u) {
 #pragma unroll
             for (int j = 0; j < T; j++) B[j] = c;
         } else {
-            core_gather<T>(ob, B);
+            core_gather<T, V0>(ob, B);
         }
 #pragma unroll
         for (int j = 0; j < T; j++) A[j] = pdiv(A[j], B[j]);
-        core_scatter<T>(od, A);
+        core_scatter<T, V0>(od, A);
         return;
     }
     float A[T];
@@ -80,7 +80,7 @@ __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
 #pragma unroll
         for (int j = 0; j < T; j++) A[j] = c;
     } else {
-        core_gather<T>(oa, A);
+        core_gather<T, V0>(oa, A);
     }
     // one copy of each long function, applied slot by slot
     ivec_t<T> a;
@@ -106,7 +106,7 @@ __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
     }
 #pragma unroll
     for (int j = 0; j < T; j++) A[j] = a[j];
-    core_scatter<T>(od, A);
+    core_scatter<T, V0>(od, A);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -118,7 +118,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One work unit: a case tile and the programs order[q0 .. q1).  The kernel
 // has exactly one call site of the core (its labels are unique); in probe
 // mode the core only reports where its handler table starts.
-template <int T, int D, int NF>
+template <int T, int D, int NF, int V0>
 __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, const float* y, int64_t N,
                                              int32_t n_load, int32_t kind, uint32_t tile, uint32_t q0,
                                              uint32_t q1) {
@@ -134,7 +134,7 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
         float x[T];
 #pragma unroll
         for (int j = 0; j < T; j++) x[j] = (64 * j + (int64_t)lane < left) ? row[64 * j + lane] : 0.0f;
-        core_scatter<T>((uint32_t)(RB * T + f * T), x);
+        core_scatter<T, V0>((uint32_t)(RB * T + f * T), x);
     }
     const uint64_t code = (uint64_t)a.code;
     for (uint32_t q = q0; q < q1; ++q) {
@@ -148,17 +148,17 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
         for (;;) {
             uint32_t pay, cst;
             uint64_t table;
-            Core<T, D, NF>::run(code, off, pay, cst, a.probe, table);
+            Core<T, D, NF, V0>::run(code, off, pay, cst, a.probe, table);
             if (a.probe) {
                 if (threadIdx.x == 0) a.probe_out[0] = table;
                 return;
             }
             if (((pay >> 24) & 15u) == CORE_OP_END) break;
-            do_exit<T>(pay, cst);
+            do_exit<T, V0>(pay, cst);
             off += 16u;
         }
         float o[T];
-        core_gather<T>(0u, o);
+        core_gather<T, V0>(0u, o);
 
         if (kind == GP_OUT_CASES) {
             float* row = a.cases_out + (int64_t)P.row * N + tile0;
@@ -202,8 +202,8 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
 // Units come either from a table (batched launches: persistent waves pull
 // them longest first from a counter, or one wave per unit) or implicitly,
 // unit u = (tile u mod tiles, program group u div tiles) over one dataset.
-template <int T, int D, int NF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(GPX_NUM_VGPR_ATTR))) void k_core(CoreArgs a) {
+template <int T, int D, int NF, int V0>
+__device__ __forceinline__ void k_core_body(const CoreArgs& a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool table = a.units != nullptr;
@@ -253,11 +253,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(GPX_NUM_VGPR_AT
             n_load = jd.n_load;
             kind = jd.kind;
         }
-        process_unit<T, D, NF>(a, X, y, N, n_load, kind, __builtin_amdgcn_readfirstlane(tile),
+        process_unit<T, D, NF, V0>(a, X, y, N, n_load, kind, __builtin_amdgcn_readfirstlane(tile),
                                __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1));
         if (a.probe || !table || !a.persistent) return;
     }
 }
+
+// One kernel per variant.  amdgpu_num_vgpr(n) lets the compiler allocate 2n
+// VGPRs on gfx950 (checked at build time against the compiler's
+// reserved-register report); the core owns v[V0 ...].
+#define GPX_KERNEL(T, D, NF, V0)                                                                        \
+    __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr((V0) / 2))) void                   \
+        k_core_##T##_##D##_##NF##_##V0(CoreArgs a) {                                                    \
+        k_core_body<T, D, NF, V0>(a);                                                                   \
+    }
+GPX_CORE_VARIANTS(GPX_KERNEL)
+#undef GPX_KERNEL
 
 __global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
 
@@ -291,10 +302,10 @@ __global__ __launch_bounds__(256) void k_reduce_one(ReduceArgs r) {
 // --------------------------------------------------------------------------
 hipError_t core_launch(int vi, const CoreArgs& a, uint32_t blocks, hipStream_t s) {
     const CoreVariantDesc& v = kCoreVariants[vi];
-#define GPX_LAUNCH(T, D, NF)                                                      \
-    if (v.t == T && v.d == D && v.nf == NF) {                                     \
-        hipLaunchKernelGGL((k_core<T, D, NF>), dim3(blocks), dim3(256), 0, s, a); \
-        return hipGetLastError();                                                 \
+#define GPX_LAUNCH(T, D, NF, V0)                                                          \
+    if (v.t == T && v.d == D && v.nf == NF && v.ncv == V0) {                              \
+        hipLaunchKernelGGL(k_core_##T##_##D##_##NF##_##V0, dim3(blocks), dim3(256), 0, s, a);\
+        return hipGetLastError();                                                         \
     }
     GPX_CORE_VARIANTS(GPX_LAUNCH)
 #undef GPX_LAUNCH
@@ -304,9 +315,10 @@ hipError_t core_launch(int vi, const CoreArgs& a, uint32_t blocks, hipStream_t s
 int core_blocks_per_cu(int vi) {
     const CoreVariantDesc& v = kCoreVariants[vi];
     int n = 0;
-#define GPX_OCC(T, D, NF)                                                                                 \
-    if (v.t == T && v.d == D && v.nf == NF) {                                                             \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_core<T, D, NF>, 256, 0) != hipSuccess) n = 1; \
+#define GPX_OCC(T, D, NF, V0)                                                                   \
+    if (v.t == T && v.d == D && v.nf == NF && v.ncv == V0) {                                    \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_core_##T##_##D##_##NF##_##V0, 256, 0) != hipSuccess) \
+            n = 1;                                                                              \
     }
     GPX_CORE_VARIANTS(GPX_OCC)
 #undef GPX_OCC

@@ -42,15 +42,19 @@ import sys
 
 SLOT = 64                 # bytes per handler slot; longer handlers take several
 LIN_REGS = 8              # register slots reserved for linear programs (and stack levels)
-NCV = 40                  # VGPRs left to the compiler; the core owns v[NCV ...]
 
-# (T, D, NF) variants.  Tree stack levels D <= 8 share the register slots.
+# (T, D, NF, NCV) variants: T case slots per lane, D stack levels, NF feature
+# slots, NCV VGPRs left to the compiler (the core owns v[NCV ...]).  Work
+# that leaves the core (sin/cos/exp/log in binary64, protected division)
+# runs in the compiler's VGPRs: programs rich in it take a variant with a
+# large NCV (fewer waves per SIMD), arithmetic programs one with NCV = 40.
 VARIANTS = [
-    (8, 6, 8),
-    (8, 8, 8),
-    (4, 8, 8),
-    (4, 8, 16),
-    (4, 12, 32),
+    (8, 6, 8, 40),
+    (8, 6, 8, 128),
+    (8, 8, 8, 40),
+    (4, 8, 8, 40),
+    (4, 8, 16, 40),
+    (4, 12, 32, 40),
 ]
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
@@ -78,12 +82,13 @@ class Handler:
         self.size += nbytes
 
 
-def gen_variant(T, D, NF):
+def gen_variant(T, D, NF, NCV):
     V0 = NCV
     FO = max(LIN_REGS, D) * T          # register/stack block, then the features
     assert FO + NF * T <= 256, "index range exceeds 8 bits"
     assert V0 + FO + NF * T <= 256
-    tag = "T%dD%dF%d" % (T, D, NF)
+    assert NCV % 8 == 0
+    tag = "T%dD%dF%dV%d" % (T, D, NF, NCV)
     hs = []
 
     def prologue(h, const=False, second_index=False):
@@ -330,9 +335,10 @@ def asm_text(T, D, NF, tag, hs):
 def gather_scatter(T, V0):
     """C++ helpers moving T slots between compiler VGPRs and the core's range."""
     out = []
+    tv = "%d, %d" % (T, V0)
     outs = ", ".join('"=v"(v[%d])' % j for j in range(T))
     movs = "".join("v_mov_b32_e32 %%%d, %s\\n\\t" % (j, vr(V0 + j)) for j in range(T))
-    out.append("template <> __device__ __forceinline__ void core_gather<%d>(uint32_t off, float (&v)[%d]) {" % (T, T))
+    out.append("template <> __device__ __forceinline__ void core_gather<%s>(uint32_t off, float (&v)[%d]) {" % (tv, T))
     out.append("#ifdef __HIP_DEVICE_COMPILE__")
     out.append('    asm volatile("s_set_gpr_idx_on %%%d, gpr_idx(SRC0)\\n\\t%ss_set_gpr_idx_off" : %s : "s"(off) : "m0");'
                % (T, movs, outs))
@@ -340,8 +346,8 @@ def gather_scatter(T, V0):
     out.append("}")
     ins = ", ".join('"v"(v[%d])' % j for j in range(T))
     movs = "".join("v_mov_b32_e32 %s, %%%d\\n\\t" % (vr(V0 + j), j + 1) for j in range(T))
-    out.append("template <> __device__ __forceinline__ void core_scatter<%d>(uint32_t off, const float (&v)[%d]) {"
-               % (T, T))
+    out.append("template <> __device__ __forceinline__ void core_scatter<%s>(uint32_t off, const float (&v)[%d]) {"
+               % (tv, T))
     out.append("#ifdef __HIP_DEVICE_COMPILE__")
     out.append('    asm volatile("s_set_gpr_idx_on %%0, gpr_idx(DST)\\n\\t%ss_set_gpr_idx_off" : : "s"(off), %s : "m0");'
                % (movs, ins))
@@ -353,31 +359,26 @@ def gather_scatter(T, V0):
 def main(out_dir):
     os.makedirs(out_dir, exist_ok=True)
     lines = ["// Generated by gen_core.py -- do not edit.", "#pragma once", ""]
-    lines.append("#define GPX_NCV %d" % NCV)
-    # amdgpu_num_vgpr(n) lets the compiler allocate 2n VGPRs on gfx950
-    # (checked at build time against the compiler's reserved-register report)
-    lines.append("#define GPX_NUM_VGPR_ATTR %d" % (NCV // 2))
-    lines.append("#define GPX_CORE_VGPR_END %d" % max(NCV + max(LIN_REGS, d) * t + nf * t for (t, d, nf) in VARIANTS))
     lines.append("#define GPX_LIN_REGS %d" % LIN_REGS)
     lines.append("#define GPX_SLOT %d" % SLOT)
     lines.append("enum CoreKind {" + ", ".join("CK_%s = %d" % (k, i) for i, k in enumerate(KINDS)) + "};")
     lines.append("")
     lines.append("#define GPX_CORE_VARIANTS(X) \\")
-    lines.append(" \\\n".join("    X(%d, %d, %d)" % v for v in VARIANTS))
+    lines.append(" \\\n".join("    X(%d, %d, %d, %d)" % v for v in VARIANTS))
     lines.append("")
     clob_s = ", ".join('"s%d"' % n for n in (63, 64, 65, 66, 67, 70, 71, 72, 76, 77))
-    lines.append("template <int T, int D, int NF> struct Core;")
-    lines.append("template <int T> __device__ void core_gather(uint32_t off, float (&v)[T]);")
-    lines.append("template <int T> __device__ void core_scatter(uint32_t off, const float (&v)[T]);")
-    for T in sorted(set(v[0] for v in VARIANTS)):
-        lines.append(gather_scatter(T, NCV))
+    lines.append("template <int T, int D, int NF, int V0> struct Core;")
+    lines.append("template <int T, int V0> __device__ void core_gather(uint32_t off, float (&v)[T]);")
+    lines.append("template <int T, int V0> __device__ void core_scatter(uint32_t off, const float (&v)[T]);")
+    for T, V0 in sorted(set((v[0], v[3]) for v in VARIANTS)):
+        lines.append(gather_scatter(T, V0))
     host = []
-    for (T, D, NF) in VARIANTS:
-        tag, V0, FO, hs, nslots = gen_variant(T, D, NF)
+    for (T, D, NF, NCV) in VARIANTS:
+        tag, V0, FO, hs, nslots = gen_variant(T, D, NF, NCV)
         text = asm_text(T, D, NF, tag, hs)
         clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
         assert NCV + FO + NF * T <= 256
-        lines.append("template <> struct Core<%d, %d, %d> {" % (T, D, NF))
+        lines.append("template <> struct Core<%d, %d, %d, %d> {" % (T, D, NF, NCV))
         lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")
         lines.append("    static __device__ __forceinline__ void run(uint64_t base, uint32_t& off, uint32_t& pay,"
                      " uint32_t& cst, uint32_t probe, uint64_t& table) {")
@@ -389,26 +390,26 @@ def main(out_dir):
         lines.append("#endif")
         lines.append("    }")
         lines.append("};")
-        host.append((T, D, NF, tag, hs, nslots))
+        host.append((T, D, NF, NCV, tag, hs, nslots))
     lines.append("")
     lines.append("struct CoreHandlerKey { uint8_t kind, op; int8_t p1, p2; };")
-    for (T, D, NF, tag, hs, nslots) in host:
+    for (T, D, NF, NCV, tag, hs, nslots) in host:
         lines.append("static const CoreHandlerKey kCoreKeys_%s[] = {" % tag)
         lines.append("    " + ", ".join("{%d,%d,%d,%d}" % (h.kind, h.op, h.p1, h.p2) for h in hs))
         lines.append("};")
         lines.append("static const uint16_t kCoreSlots_%s[] = {" % tag)
         lines.append("    " + ", ".join(str(h.slot) for h in hs))
         lines.append("};")
-    lines.append("struct CoreVariantDesc { int t, d, nf; const CoreHandlerKey* keys; const uint16_t* slots; int n; int table_bytes; };")
+    lines.append("struct CoreVariantDesc { int t, d, nf, ncv; const CoreHandlerKey* keys; const uint16_t* slots; int n; int table_bytes; };")
     lines.append("static const CoreVariantDesc kCoreVariants[] = {")
-    for (T, D, NF, tag, hs, nslots) in host:
-        lines.append("    {%d, %d, %d, kCoreKeys_%s, kCoreSlots_%s, %d, %d}," % (T, D, NF, tag, tag, len(hs), nslots * SLOT))
+    for (T, D, NF, NCV, tag, hs, nslots) in host:
+        lines.append("    {%d, %d, %d, %d, kCoreKeys_%s, kCoreSlots_%s, %d, %d}," % (T, D, NF, NCV, tag, tag, len(hs), nslots * SLOT))
     lines.append("};")
     path = os.path.join(out_dir, "core_gen.inc")
     with open(path + ".tmp", "w") as f:
         f.write("\n".join(lines) + "\n")
     os.replace(path + ".tmp", path)
-    for (T, D, NF, tag, hs, nslots) in host:
+    for (T, D, NF, NCV, tag, hs, nslots) in host:
         print("%s: %d handlers, %d slots (%d KiB)" % (tag, len(hs), nslots, nslots * SLOT // 1024))
     return path
 

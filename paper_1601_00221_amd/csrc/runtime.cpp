@@ -166,7 +166,11 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
             if ((t & 0xFF) == GP_VAR) max_feat = std::max<int32_t>(max_feat, (int32_t)((uint32_t)t >> 8));
         }
         uint32_t cost = 0;
-        for (int32_t i = 0; i < st.n_instr; i++) cost += op_cost(pd.code[2 * (w + i)] & 15u);
+        for (int32_t i = 0; i < st.n_instr; i++) {
+            const uint32_t op = pd.code[2 * (w + i)] & 15u;
+            cost += op_cost(op);
+            pd.n_exit += (op >= GP_PDIV && op <= GP_PLOG);
+        }
         if (w > 0xFFFFFFFFll - 2 * (int64_t)st.n_instr)
             return fail(GP_E_INVAL, "programs exceed 2^32 device words");
         DevProg& d = pd.progs[p];
@@ -230,6 +234,7 @@ gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cs
             const uint32_t wd = src[i];
             const int op = wd & 0xFF;
             cost += op_cost(op);
+            pd.n_exit += (op >= GP_PDIV);
             const int na = op < GP_SIN ? 2 : 1;
             for (int q = 0; q < na; q++) {
                 const int id = (int)((wd >> (16 + 8 * q)) & 0xFF);
@@ -367,7 +372,9 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     if (pd.n_prog == 0) return GP_OK;
     if (pd.n_load > GP_MAX_FEAT)
         return fail(GP_E_INVAL, "programs read feature %d; at most %d features are supported", pd.n_load - 1, GP_MAX_FEAT);
-    const int vi = opt && opt->variant >= 0 ? opt->variant : pick_core_variant(pd.n_load, pd.max_depth);
+    const int vi = opt && opt->variant >= 0
+                       ? opt->variant
+                       : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_exit / pd.n_instr : 0.0);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth)
