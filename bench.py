@@ -4,7 +4,7 @@
 
 A step is one evaluation of a resident population on a resident case matrix:
 the evaluation kernel (decode, 2D-stack interpretation, per-case error,
-per-tile partial sums) and the fixed-order fitness reduction.  Programs and
+per-block partial sums) and the fixed-order fitness reduction.  Programs and
 cases are uploaded before the timed region.  Prints one JSON line.
 
 Workloads (synthetic, seeded):
@@ -14,11 +14,29 @@ Workloads (synthetic, seeded):
   linear       4096 register programs of 32-256 instructions, 8 registers,
                16 features x 1,048,576 cases ~N(0,1), hit count
   tiny-tree    100 ramped half-and-half trees, 1024 cases, sum |error|
+  batched      10,000 programs in 40 populations (trees and register programs,
+               lognormal lengths 8-1024) over three resident case matrices of
+               4096 / 65536 / 1,048,576 cases x 8 features, one autotuned
+               persistent launch per step; compared with one launch per
+               population
+  served       32 concurrent GP runs in a closed loop submitting population
+               evaluations to the continuous-batching server; p50/p99 latency
+               and throughput, compared with one launch per request
+  copy-calibration
+               a plain 256 MiB device copy, three times: the reference for
+               scaling the FETCH_SIZE / WRITE_SIZE counters to bytes
+
+The roofline's HBM traffic comes from the counter records under profiles/
+(lines starting "traffic-record:"); a record only counts when it names this
+workload and the digest of the kernel's current sources.
 """
 import argparse
+import glob
 import json
+import math
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -26,7 +44,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_T = 157.3   # MI355X vector FP32 peak, TFLOP/s
+PEAK_FP32_T = 157.3   # MI355X vector FP32 peak, TFLOP/s (one GP operation counted as one FP32 operation)
 
 
 def log(*a):
@@ -46,30 +64,35 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def gpu_targets(w, Xd):
-    """Target values of the workload's target tree, computed by the library
-    itself (the first candidate whose values are finite and below 1e6)."""
+def gpu_targets(target, X, noise):
+    """Target values: the first candidate target tree whose values on X are
+    all finite and below 1e6 in magnitude, computed by the library itself,
+    plus the noise."""
     import torch
     import paper_1601_00221_amd as gp
-    for i in range(w.target.n_prog):
-        t = w.target.subset([i])
-        out = torch.empty((1, Xd.shape[1]), dtype=torch.float32, device="cuda")
-        gp.gp_eval_tree(t.tok, t.cst, t.off, Xd, None, "cases", out)
+    for i in range(target.n_prog):
+        t = target.subset([i])
+        out = torch.empty((1, X.shape[1]), dtype=torch.float32, device="cuda")
+        gp.gp_eval_tree(t.tok, t.cst, t.off, X, None, "cases", out)
         v = out[0]
         if bool(torch.isfinite(v).all()) and float(v.abs().max()) < 1e6:
-            return (v + torch.from_numpy(w.noise).cuda()).contiguous()
+            return (v + torch.from_numpy(noise).cuda()).contiguous()
     raise RuntimeError("no acceptable target tree")
 
 
-def cpu_baseline(w, y_host, budget_s=10.0):
-    """The oracle as it stands, on the host cores, on a bounded sample of
-    the same workload: every k-th program over all cases."""
-    import oracle
+def host_cores():
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    return max(1, min(cores, 16))
+
+
+def cpu_baseline(w, y_host, budget_s=10.0):
+    """The oracle as it stands, on the host cores, on a bounded sample of
+    the same workload: evenly spaced programs over all cases."""
+    import oracle
+    cores = host_cores()
     tree = hasattr(w, "target")
     P = w.pop.n_prog
     N = w.X.shape[1]
@@ -79,19 +102,15 @@ def cpu_baseline(w, y_host, budget_s=10.0):
         t0 = time.perf_counter()
         if tree:
             oracle.eval_tree(sub.tok, sub.cst, sub.off, w.X, y_host, w.kind, threads=cores)
-            ops = int(np.sum(sub.sizes())) * N
         else:
             oracle.eval_linear(sub.code, sub.off, sub.cst, sub.cst_off, sub.n_reg, w.X, y_host, w.kind,
                                threads=cores)
-            ops = int(np.sum(sub.sizes())) * N
-        return ops, time.perf_counter() - t0
+        return int(np.sum(sub.sizes())) * N, time.perf_counter() - t0
 
     probe = np.linspace(0, P - 1, min(P, 2 * cores)).astype(int)
     ops, dt = run(probe)
-    rate = ops / max(dt, 1e-9)
-    want_ops = rate * budget_s
-    mean_ops = ops / len(probe)
-    n = int(min(P, max(len(probe), want_ops / max(mean_ops, 1))))
+    want_ops = ops / max(dt, 1e-9) * budget_s
+    n = int(min(P, max(len(probe), want_ops / max(ops / len(probe), 1))))
     idx = np.linspace(0, P - 1, n).astype(int)
     ops, dt = run(idx)
     return {"value": ops / dt, "unit": "GPop/s", "cores": cores, "kind": "oracle",
@@ -99,31 +118,73 @@ def cpu_baseline(w, y_host, budget_s=10.0):
                       % (n, P, N, ops, dt)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="scale-tree")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the evaluator is built and measured on a single MI355X "
-              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def traffic_record(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from a committed counter
+    summary measured with the kernel's current sources, else None."""
+    import paper_1601_00221_amd as gp
+    digest = gp.kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                line = line.strip().strip("`")
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
+                if kv.get("workload") == workload and kv.get("kernel") == kernel and kv.get("source") == digest:
+                    return int(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
+
+def roofline(gpop_per_launch, launch_s, kernel, workload):
+    achieved = gpop_per_launch / launch_s / 1e12
+    traffic, src = traffic_record(workload, kernel)
+    r = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_T, "unit": "TFLOP/s",
+         "frac": achieved / PEAK_FP32_T, "traffic": traffic, "kernel": kernel,
+         "kernel_ms": launch_s * 1e3}
+    if traffic is not None:
+        r["traffic_source"] = src
+        r["hbm_gbs"] = traffic / launch_s / 1e9
+    return r
+
+
+def base_result(args, value, step_s, config):
+    return {
+        "metric": "GPop/s (GP ops/sec) + % vector-FP32 peak",
+        "value": value,
+        "unit": "GPop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": config,
+        "pct_vector_fp32_peak": 100.0 * value / (PEAK_FP32_T * 1e12),
+    }
+
+
+def kernel_name(vi):
+    import paper_1601_00221_amd as gp
+    return gp.variants()[vi]["kernel"] if vi >= 0 else "k_core"
+
+
+# ----------------------------------------------------------------------------
+# one population on one case matrix
+# ----------------------------------------------------------------------------
+def bench_single(args):
     import torch
     import paper_1601_00221_amd as gp
 
-    log("workload", args.workload)
     w = make_workload(args.workload)
     N = w.X.shape[1]
     P = w.pop.n_prog
     Xd = torch.from_numpy(w.X).cuda()
     tree = hasattr(w, "target")
     if tree:
-        yd = gpu_targets(w, Xd)
+        yd = gpu_targets(w.target, Xd, w.noise)
         ps = gp.ProgSet.tree(w.pop.tok, w.pop.cst, w.pop.off, w.X.shape[0])
     else:
         yd = torch.from_numpy(w.y).cuda()
@@ -147,7 +208,6 @@ def main():
     step_s = (t1 - t0) / args.steps
     value = gpop_per_step / step_s
     kern_s = kernel_ms / 1e3 / max(n_launch, 1)
-    achieved = gpop_per_step / kern_s / 1e12
     log("step %.3f ms, kernel %.3f ms, %.3f T GPop/s" % (step_s * 1e3, kern_s * 1e3, value / 1e12))
 
     # the same evaluation through the one-shot call: host lowering + PCIe upload included
@@ -162,32 +222,222 @@ def main():
     torch.cuda.synchronize()
     call_s = (time.perf_counter() - c0) / reps
 
-    res = {
-        "metric": "GPop/s (GP ops/sec) + % vector-FP32 peak",
-        "value": value,
-        "unit": "GPop/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": step_s * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "n_prog": P, "n_cases": N, "n_feat": int(w.X.shape[0]),
-                   "fitness": w.kind, "gpop_per_step": gpop_per_step},
-        "pct_vector_fp32_peak": 100.0 * value / (PEAK_FP32_T * 1e12),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_T, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_T, "traffic": None,
-                     "kernel": "k_eval", "kernel_ms": kern_s * 1e3},
-        "call_gpops_per_s": gpop_per_step / call_s,
-    }
+    config = {"workload": w.name, "n_prog": P, "n_cases": N, "n_feat": int(w.X.shape[0]),
+              "fitness": w.kind, "gpop_per_step": gpop_per_step}
+    res = base_result(args, value, step_s, config)
+    res["roofline"] = roofline(gpop_per_step, kern_s, kernel_name(info["variant"]), w.name)
+    res["call_gpops_per_s"] = gpop_per_step / call_s
     if not args.no_cpu:
-        y_host = yd.cpu().numpy()
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline(w, y_host, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(w, yd.cpu().numpy(), args.cpu_budget)
     ps.close()
+    return res
+
+
+# ----------------------------------------------------------------------------
+# batched: several populations and case matrices in one persistent launch
+# ----------------------------------------------------------------------------
+def bench_batched(args):
+    import torch
+    import paper_1601_00221_amd as gp
+    import synth
+
+    w = synth.batched_workload()
+    dd = []
+    for X, tgt, noise in zip(w.X, w.target, w.noise):
+        Xd = torch.from_numpy(X).cuda()
+        dd.append((Xd, gpu_targets(tgt, Xd, noise)))
+    Ns = [X.shape[1] for X in w.X]
+    outs = [gp.out_tensor(j.kind, j.pop.n_prog, 0) for j in w.jobs]
+    jobs = [gp.make_job(j.pop, j.dataset, j.kind, o) for j, o in zip(w.jobs, outs)]
+    gpop_per_step = sum(int(j.pop.sizes().sum()) * Ns[j.dataset] for j in w.jobs)
+
+    log("autotuning ...")
+    best, best_ms = gp.gp_tune_batch(dd, jobs, reps=3)
+    log("tuned", best.as_dict(), "%.3f ms" % best_ms)
+    for _ in range(args.warmup):
+        gp.gp_eval_batch(dd, jobs)
+    torch.cuda.synchronize()
+    gp.timing_read(reset=True)
+    gp.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gp.gp_eval_batch(dd, jobs)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    gp.timing_enable(False)
+    n_launch, kernel_ms = gp.timing_read(reset=True)
+    kern_s = kernel_ms / 1e3 / max(n_launch, 1)
+    batched = [o.clone() for o in outs]
+
+    # the comparison: one launch per population, serialised on one stream
+    def unbatched():
+        for j, o in zip(w.jobs, outs):
+            X, y = dd[j.dataset]
+            p = j.pop
+            if hasattr(p, "tok"):
+                gp.gp_eval_tree(p.tok, p.cst, p.off, X, y, j.kind, o)
+            else:
+                gp.gp_eval_linear(p.code, p.off, p.cst, p.cst_off, p.n_reg, X, y, j.kind, o)
+    unbatched()
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 5))
+    u0 = time.perf_counter()
+    for _ in range(reps):
+        unbatched()
+    torch.cuda.synchronize()
+    unb_s = (time.perf_counter() - u0) / reps
+    same = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(batched, outs))
+    value = gpop_per_step / step_s
+    log("batched %.3f ms/step (%.3f T GPop/s), one launch per population %.3f ms, identical=%s"
+        % (step_s * 1e3, value / 1e12, unb_s * 1e3, same))
+    config = {"workload": w.name, "n_prog": w.meta["n_prog"], "n_jobs": w.meta["n_jobs"],
+              "n_cases": Ns, "n_feat": w.meta["n_feat"], "fitness": "mse", "gpop_per_step": gpop_per_step,
+              "tuned": best.as_dict()}
+    res = base_result(args, value, step_s, config)
+    res["roofline"] = roofline(gpop_per_step, kern_s, kernel_name(best.variant), w.name)
+    res["unbatched"] = {"gpops_per_s": gpop_per_step / unb_s, "ms_per_step": unb_s * 1e3,
+                        "launches_per_step": len(jobs), "speedup_of_batched": unb_s / step_s,
+                        "fitness_identical": same}
+    return res
+
+
+# ----------------------------------------------------------------------------
+# served: closed-loop GP runs against the continuous-batching server
+# ----------------------------------------------------------------------------
+def bench_served(args):
+    import torch
+    import paper_1601_00221_amd as gp
+    import synth
+
+    w = synth.served_workload(n_req=args.requests)
+    log("served workload generated")
+    data = []
+    for r in w.runs:
+        Xd = torch.from_numpy(r.X).cuda()
+        data.append((Xd, gpu_targets(r.target, Xd, r.noise)))
+    reqs = []      # per run: list of (pop, gpop)
+    for ri, r in enumerate(w.runs):
+        F, N = r.X.shape
+        lst = []
+        for form, start, P in r.requests:
+            pool = w.tree_pool if form == 0 else w.lin_pool
+            pop = synth.remap_features(synth.pool_slice(pool, start, P), F)
+            lst.append((pop, int(pop.sizes().sum()) * N))
+        reqs.append(lst)
+    total_gpop = sum(g for lst in reqs for _, g in lst)
+    n_warm = max(0, min(args.warmup, args.requests - 1))
+
+    def run_mode(batching):
+        srv = gp.Server(batching=batching)
+        ids = [srv.add_dataset(X, y) for X, y in data]
+        lat = []
+        gpop_meas = [0]
+        lock = threading.Lock()
+        t_first = [None]
+        t_last = [0.0]
+        errors = []
+        results = {}
+
+        def client(ri):
+            try:
+                for k, (pop, g) in enumerate(reqs[ri]):
+                    out = gp.out_tensor("mse", pop.n_prog, 0)
+                    job = gp.make_job(pop, ids[ri], "mse", out)
+                    t0 = time.perf_counter()
+                    tk = srv.submit(job)
+                    rc = srv.wait(tk)
+                    t1 = time.perf_counter()
+                    if rc != 0:
+                        raise gp.GPError(rc, gp.last_error())
+                    srv.release(tk)
+                    results[(ri, k)] = out
+                    if k >= n_warm:
+                        with lock:
+                            lat.append(t1 - t0)
+                            gpop_meas[0] += g
+                            if t_first[0] is None or t0 < t_first[0]:
+                                t_first[0] = t0
+                            t_last[0] = max(t_last[0], t1)
+                    time.sleep(float(w.runs[ri].think_s[k]))
+            except Exception as e:   # reported after the join
+                errors.append(repr(e))
+
+        th = [threading.Thread(target=client, args=(ri,)) for ri in range(len(w.runs))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        st = srv.stats()
+        srv.close()
+        if errors:
+            raise RuntimeError("served run failed: " + errors[0])
+        lat = np.sort(np.array(lat))
+        span = t_last[0] - t_first[0]
+        return {"gpops_per_s": gpop_meas[0] / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "requests": int(len(lat)),
+                "span_s": span, "mean_batch": st["mean_batch"], "batches": st["batches"]}, results
+
+    gp.timing_read(reset=True)
+    gp.timing_enable(True)
+    served, res_b = run_mode(True)
+    torch.cuda.synchronize()
+    gp.timing_enable(False)
+    n_launch, kernel_ms = gp.timing_read(reset=True)
+    log("served", served)
+    single, res_s = run_mode(False)
+    log("one launch per request", single)
+    same = all(torch.equal(res_b[k].view(torch.int32), res_s[k].view(torch.int32)) for k in res_b)
+    config = {"workload": w.name, "n_runs": len(w.runs), "requests_per_run": args.requests,
+              "warmup_requests_per_run": n_warm, "gpop_total": total_gpop, "fitness": "mse",
+              "arrivals": "closed loop, Exp(2 ms) think time"}
+    res = base_result(args, served["gpops_per_s"], served["span_s"] / max(served["requests"], 1), config)
+    res["steps"] = served["requests"]
+    res["served"] = served
+    res["unbatched"] = dict(single, speedup_of_served=served["gpops_per_s"] / single["gpops_per_s"],
+                            fitness_identical=same)
+    # kernel time over all batched launches of the served run (warm-up included)
+    all_gpop = total_gpop
+    res["roofline"] = roofline(all_gpop / max(n_launch, 1), kernel_ms / 1e3 / max(n_launch, 1), "k_core", w.name)
+    res["roofline"]["note"] = "mean over the served run's %d launches, several kernel variants" % n_launch
+    return res
+
+
+def copy_calibration():
+    """A plain device copy of known size for scaling the HBM counters."""
+    import torch
+    n = 64 << 20
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="scale-tree")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--requests", type=int, default=12, help="served: requests per run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the evaluator is built and measured on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    log("workload", args.workload)
+    if args.workload == "copy-calibration":
+        res = copy_calibration()
+    elif args.workload == "batched":
+        res = bench_batched(args)
+    elif args.workload == "served":
+        res = bench_served(args)
+    else:
+        res = bench_single(args)
     print(json.dumps(res), flush=True)
 
 

@@ -123,6 +123,8 @@ typedef struct {
     int32_t max_depth;         /* stack levels needed (trees) */
     int64_t n_instr;           /* device instructions over all programs */
     int64_t n_gpop;            /* GP operations per fitness case: tree nodes, or linear instructions */
+    int32_t variant;           /* kernel variant gp_progset_eval launches for the set */
+    int32_t pad;
 } gp_progset_info;
 
 /* Same program arguments as gp_eval_tree / gp_eval_linear.  The upload is
@@ -191,10 +193,12 @@ gp_status gp_eval_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
  * the environment names a file in GP2D_TUNE_CACHE, in that JSON file. */
 gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, int32_t n_jobs, int32_t reps,
                         gp_batch_config* best, double* best_ms, void* stream);
-/* Compiled kernel variants: tile width t (case slots per lane), stack levels
- * and feature slots. */
+/* Compiled kernel variants: tile width t (case slots per lane), stack levels,
+ * feature slots and the VGPRs left to compiled code (the interpreter core
+ * owns the VGPRs from that number up).  The variant's kernel is named
+ * k_core_<t>_<depth>_<n_feat>_<vgprs>.  Any pointer may be NULL. */
 int32_t gp_num_variants(void);
-gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat);
+gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: concurrent GP runs submit population evaluations against        */

@@ -39,7 +39,8 @@ class LowerStats(C.Structure):
 
 class ProgsetInfo(C.Structure):
     _fields_ = [("n_prog", C.c_int32), ("form", C.c_int32), ("n_feat", C.c_int32),
-                ("max_depth", C.c_int32), ("n_instr", C.c_int64), ("n_gpop", C.c_int64)]
+                ("max_depth", C.c_int32), ("n_instr", C.c_int64), ("n_gpop", C.c_int64),
+                ("variant", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -66,7 +67,7 @@ def lib():
             "gp_timing_read": [P, P, C.c_int],
             "gp_eval_batch": [P, i32, P, i32, P, P],
             "gp_tune_batch": [P, i32, P, i32, i32, P, P, P],
-            "gp_variant_info": [i32, P, P, P],
+            "gp_variant_info": [i32, P, P, P, P],
             "gp_serve_create": [P, P],
             "gp_serve_add_dataset": [P, P, i32, i64, P, P],
             "gp_serve_submit": [P, P, P],
@@ -331,9 +332,10 @@ def variants():
     L = lib()
     out = []
     for i in range(L.gp_num_variants()):
-        t, d, f = C.c_int32(), C.c_int32(), C.c_int32()
-        check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f)))
-        out.append({"t": t.value, "depth": d.value, "n_feat": f.value})
+        t, d, f, v = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f), C.byref(v)))
+        out.append({"t": t.value, "depth": d.value, "n_feat": f.value, "vgprs": v.value,
+                    "kernel": "k_core_%d_%d_%d_%d" % (t.value, d.value, f.value, v.value)})
     return out
 
 
@@ -431,3 +433,19 @@ def out_tensor(kind, n_prog, n_cases, device="cuda"):
     if k == GP_OUT_CASES:
         return torch.empty((n_prog, n_cases), dtype=torch.float32, device=device)
     return torch.empty(n_prog, dtype=torch.float32, device=device)
+
+
+# Sources that decide the evaluation kernel's machine code and launch shape.
+KERNEL_SOURCES = ("csrc/gen_core.py", "csrc/core_kernels.hip", "csrc/core_kernels.h", "csrc/core_host.cpp",
+                  "csrc/core_host.h", "csrc/runtime.cpp", "build.py")
+
+
+def kernel_source_digest() -> str:
+    """Short SHA-256 over the evaluation kernel's sources: a measurement taken
+    with another digest describes a different kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(_HERE, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read() + b"\0")
+    return h.hexdigest()[:16]

@@ -502,12 +502,13 @@ gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
 
 int32_t gp_num_variants(void) { return core_variants(); }
 
-gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat) {
+gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs) {
     clear_error();
     if (i < 0 || i >= core_variants()) return fail(GP_E_INVAL, "variant %d does not exist", i);
     if (t) *t = core_variant_t(i);
     if (depth) *depth = core_variant_d(i);
     if (n_feat) *n_feat = core_variant_nf(i);
+    if (vgprs) *vgprs = core_variant_ncv(i);
     return GP_OK;
 }
 

@@ -530,6 +530,9 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->max_depth = ps->pd.max_depth;
     info->n_instr = ps->pd.n_instr;
     info->n_gpop = ps->pd.n_gpop;
+    info->variant = pick_core_variant(ps->pd.n_load, ps->pd.max_depth,
+                                      ps->pd.n_instr ? (double)ps->pd.n_exit / ps->pd.n_instr : 0.0);
+    info->pad = 0;
     return GP_OK;
 }
 

@@ -379,3 +379,164 @@ def linear_workload(seed: int = 3, n_prog: int = 4096, n_cases: int = 1 << 20,
 
 def wl_scaled_tree(seed, n_prog, n_cases, n_feat=8, fset=FULL, max_size=256):
     return scale_tree_workload(seed, n_prog, n_cases, n_feat, fset, max_size)
+
+
+# ----------------------------------------------------------------------------
+# Batched and served workloads
+# ----------------------------------------------------------------------------
+@dataclass
+class BatchJobSpec:
+    pop: object                # TreePop or LinearPop
+    dataset: int
+    kind: str
+
+
+@dataclass
+class BatchedWorkload:
+    name: str
+    X: list                    # per dataset, (F, N) float32
+    target: list               # per dataset, TreePop of candidate target trees
+    noise: list                # per dataset, (N,) float32
+    jobs: list                 # BatchJobSpec
+    meta: dict = field(default_factory=dict)
+
+
+def batched_workload(seed: int = 4, n_prog: int = 10000, n_jobs: int = 40,
+                     sizes=(4096, 65536, 1 << 20), n_feat: int = 8) -> BatchedWorkload:
+    """Several GP populations over three resident case matrices, evaluated in
+    one launch: 10,000 programs split into 40 populations of 250, even ones
+    PTC2 trees over the full function set, odd ones register programs over
+    {+,-,*,/p} with 8 registers and 2 constants; program lengths
+    round(lognormal(ln 64, 1)) clipped to [8, 1024]; each population's case
+    matrix drawn uniformly from the three (4096 / 65,536 / 1,048,576 cases x
+    8 features ~U(-5,5)); targets from a random tree plus N(0, 0.01) noise;
+    fitness = MSE."""
+    rng = rng_for(seed)
+    X, target, noise = [], [], []
+    p_const = 1.0 / (n_feat + 1)
+    for n in sizes:
+        X.append(uniform_cases(rng, n_feat, n, -5.0, 5.0))
+        target.append(trees_from_lists([ptc2_tree(rng, int(rng.integers(8, 33)), FULL, n_feat, p_const)
+                                        for _ in range(16)]))
+        noise.append(gaussian_noise(rng, n, 0.01))
+    per = n_prog // n_jobs
+    jobs = []
+    for j in range(n_jobs):
+        lens = lognormal_lengths(rng, per, math.log(64.0), 1.0, 8, 1024)
+        ds = int(rng.integers(len(sizes)))
+        if j % 2 == 0:
+            pop = ptc2_population(rng, per, FULL, n_feat, 0, 0, p_const, sizes=lens)
+        else:
+            pop = linear_population(rng, per, 0, 0, BASIC, 8, n_feat, n_const=2, lengths=lens)
+        jobs.append(BatchJobSpec(pop, ds, "mse"))
+    return BatchedWorkload("batched-%dprogs-%djobs-N%s-F%d" % (n_prog, n_jobs, "/".join(str(s) for s in sizes), n_feat),
+                           X, target, noise, jobs,
+                           dict(n_prog=n_prog, n_jobs=n_jobs, sizes=list(sizes), n_feat=n_feat))
+
+
+@dataclass
+class ServedRun:
+    X: np.ndarray              # (F, N) float32
+    target: TreePop            # candidate target trees
+    noise: np.ndarray
+    requests: list             # per request: (form, start, n_prog) into the program pools
+    think_s: np.ndarray        # think time after each request, seconds
+
+
+@dataclass
+class ServedWorkload:
+    name: str
+    runs: list                 # ServedRun
+    tree_pool: TreePop         # programs over MAX_SERVE_FEAT features
+    lin_pool: LinearPop
+    meta: dict = field(default_factory=dict)
+
+
+MAX_SERVE_FEAT = 32
+
+
+def served_workload(seed: int = 5, n_runs: int = 32, n_req: int = 16, pool: int = 8192,
+                    n_lo: int = 1000, n_hi: int = 2_000_000, pop_lo: int = 64, pop_hi: int = 8192,
+                    len_hi: int = 512, think_mean_s: float = 0.002) -> ServedWorkload:
+    """Concurrent GP runs, each with its own resident case matrix: cases
+    log-uniform in [1k, 2M], features uniform in {4..32}, X ~U(-5,5), targets
+    from a random tree plus N(0, 0.01) noise, MSE.  Each run issues n_req
+    population evaluations in a closed loop (submit, wait for the result,
+    think for an Exp(2 ms) time): population log-uniform in [64, 8192],
+    program lengths U{1..512}, tree or register form with probability 1/2.
+    Programs are slices of two shared pools drawn over 32 features; a request
+    to a run with F features reads feature k as k mod F (remap_features)."""
+    rng = rng_for(seed)
+    p_const = 1.0 / (MAX_SERVE_FEAT + 1)
+    tree_pool = ptc2_population(rng, pool, FULL, MAX_SERVE_FEAT, 1, len_hi, p_const)
+    lin_pool = linear_population(rng, pool, 1, len_hi, BASIC, 8, MAX_SERVE_FEAT, n_const=2)
+    runs = []
+    for r in range(n_runs):
+        N = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        F = int(rng.integers(4, MAX_SERVE_FEAT + 1))
+        X = uniform_cases(rng, F, N, -5.0, 5.0)
+        tgt = trees_from_lists([ptc2_tree(rng, int(rng.integers(8, 33)), FULL, F, 1.0 / (F + 1))
+                                for _ in range(16)])
+        noise = gaussian_noise(rng, N, 0.01)
+        reqs = []
+        for _ in range(n_req):
+            P = int(round(math.exp(rng.uniform(math.log(pop_lo), math.log(pop_hi)))))
+            form = int(rng.integers(2))
+            start = int(rng.integers(pool))
+            reqs.append((form, start, P))
+        think = rng.exponential(think_mean_s, size=n_req)
+        runs.append(ServedRun(X, tgt, noise, reqs, think))
+    return ServedWorkload("served-%druns-%dreq" % (n_runs, n_req), runs, tree_pool, lin_pool,
+                          dict(n_runs=n_runs, n_req=n_req, pool=pool))
+
+
+def pool_slice(pool, start: int, n: int):
+    """Programs start, start+1, ... (wrapping) of a TreePop / LinearPop."""
+    P = pool.n_prog
+    if n > P:
+        raise ValueError("slice longer than the pool")
+    pieces = [(start, min(P, start + n))]
+    if start + n > P:
+        pieces.append((0, start + n - P))
+    if hasattr(pool, "tok"):
+        tok, cst, off = [], [], [np.zeros(1, np.int64)]
+        base = 0
+        for a, b in pieces:
+            lo, hi = int(pool.off[a]), int(pool.off[b])
+            tok.append(pool.tok[lo:hi])
+            cst.append(pool.cst[lo:hi])
+            off.append(pool.off[a + 1:b + 1] - lo + base)
+            base += hi - lo
+        return TreePop(np.concatenate(tok), np.concatenate(cst), np.concatenate(off))
+    code, off, cst, coff = [], [np.zeros(1, np.int64)], [], [np.zeros(1, np.int64)]
+    base = cbase = 0
+    for a, b in pieces:
+        lo, hi = int(pool.off[a]), int(pool.off[b])
+        clo, chi = int(pool.cst_off[a]), int(pool.cst_off[b])
+        code.append(pool.code[lo:hi])
+        cst.append(pool.cst[clo:chi])
+        off.append(pool.off[a + 1:b + 1] - lo + base)
+        coff.append(pool.cst_off[a + 1:b + 1] - clo + cbase)
+        base += hi - lo
+        cbase += chi - clo
+    return LinearPop(np.concatenate(code), np.concatenate(off), np.concatenate(cst), np.concatenate(coff),
+                     pool.n_reg)
+
+
+def remap_features(pop, n_feat: int):
+    """The same programs reading feature k mod n_feat instead of feature k."""
+    if hasattr(pop, "tok"):
+        tok = pop.tok.copy()
+        v = (tok & 0xFF) == VAR
+        k = tok >> 8
+        tok[v] = VAR | ((k[v] % n_feat) << 8)
+        return TreePop(tok, pop.cst, pop.off)
+    code = pop.code.copy()
+    R = pop.n_reg
+    out = code
+    for sh in (16, 24):
+        s = (code >> sh) & 0xFF
+        feat = (s >= R) & (s < SRC_CONST_BASE)
+        s2 = np.where(feat, R + (s - R) % n_feat, s)
+        out = (out & ~np.uint32(0xFF << sh)) | (s2.astype(np.uint32) << sh)
+    return LinearPop(out.astype(np.uint32), pop.off, pop.cst, pop.cst_off, pop.n_reg)
