@@ -338,6 +338,7 @@ def bench_served(args):
         t_last = [0.0]
         errors = []
         results = {}
+        done = [0]
 
         def client(ri):
             try:
@@ -352,6 +353,11 @@ def bench_served(args):
                         raise gp.GPError(rc, gp.last_error())
                     srv.release(tk)
                     results[(ri, k)] = out
+                    with lock:
+                        done[0] += 1
+                        if done[0] % 32 == 0:
+                            log("  %s: %d requests done" % ("served" if batching else "one launch per request",
+                                                           done[0]))
                     if k >= n_warm:
                         with lock:
                             lat.append(t1 - t0)
@@ -423,7 +429,7 @@ def main():
     ap.add_argument("--workload", default="scale-tree")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
-    ap.add_argument("--requests", type=int, default=12, help="served: requests per run")
+    ap.add_argument("--requests", type=int, default=10, help="served: requests per run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the evaluator is built and measured on a single MI355X "

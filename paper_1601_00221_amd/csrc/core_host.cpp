@@ -49,7 +49,7 @@ int pick_core_variant(int n_load, int depth, double exit_frac) {
     const bool heavy = exit_frac > 0.2;
     int best = -1;
     auto score = [&](const CoreVariantDesc& v) {
-        const int fit = heavy ? (v.ncv >= 96) : (v.ncv <= 64);
+        const int fit = heavy ? (v.ncv >= 80) : (v.ncv <= 64);
         return fit * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
     };
     for (int i = 0; i < core_variants(); i++) {

@@ -55,6 +55,9 @@ VARIANTS = [
     (4, 8, 8, 40),
     (4, 8, 16, 40),
     (4, 12, 32, 40),
+    (8, 8, 8, 128),
+    (4, 8, 16, 128),
+    (4, 12, 32, 80),
 ]
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
