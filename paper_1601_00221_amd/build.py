@@ -61,8 +61,21 @@ def _check_reserved(src: str):
             raise RuntimeError("the compiler may allocate core VGPRs %s (variant %s)" % (missing[:8], (t, d, nf, ncv)))
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True if obj is older than src, any header, or the generated core."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src), os.path.join(GEN, "core_gen.inc"), os.path.abspath(__file__),
+            os.path.join(os.path.dirname(PKG), "include", "gp.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    return any(os.path.exists(d) and os.path.getmtime(d) > t for d in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *FLAGS, "-I", GEN, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -70,7 +83,9 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only those older than their
+    inputs, for development) and link libgp.so."""
     os.makedirs(BUILD, exist_ok=True)
     # generate the hand-written interpreter core for every kernel variant
     sys.path.insert(0, CSRC)
@@ -78,12 +93,25 @@ def build(verbose: bool = False) -> str:
         import gen_core
     finally:
         sys.path.pop(0)
-    gen_core.main(GEN)
+    inc = os.path.join(GEN, "core_gen.inc")
+    old = open(inc).read() if os.path.exists(inc) else None
+    if incremental and old is not None:
+        tmp = GEN + ".tmp"
+        gen_core.main(tmp)
+        new = open(os.path.join(tmp, "core_gen.inc")).read()
+        if new != old:
+            gen_core.main(GEN)
+        shutil.rmtree(tmp, ignore_errors=True)
+    else:
+        gen_core.main(GEN)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
-        check = ex.submit(_check_reserved, "core_kernels.hip")
-        objs = list(ex.map(_compile, srcs))
-        check.result()
+        check = None
+        if not incremental or _stale("core_kernels.hip", os.path.join(BUILD, "core_kernels.o")):
+            check = ex.submit(_check_reserved, "core_kernels.hip")
+        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
+        if check is not None:
+            check.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -100,5 +128,5 @@ def clean() -> None:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

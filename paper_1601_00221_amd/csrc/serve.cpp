@@ -39,6 +39,7 @@ struct Request {
     void* out = nullptr;
     size_t need = 0;
     int64_t gpop = 0;
+    int32_t variant = -1;      // kernel variant the request runs with, alone or fused
     ReqState state = RQ_QUEUED;
     gp_status status = GP_OK;
     Clock::time_point t_submit, t_done;
@@ -131,7 +132,9 @@ static gp_status launch_batch_locked(Server& S, int k, std::vector<std::shared_p
         f.fake_ms = S.cfg.dry_run_gpops > 0 ? gpop / S.cfg.dry_run_gpops * 1e3 : 0.0;
         return GP_OK;
     }
+    // every request of a batch has the same variant (the scheduler fuses only those)
     gp_batch_config c = default_config(refs);
+    c.variant = reqs[0]->variant;
     if (c.variant < 0) return fail(GP_E_DEPTH, "no kernel variant can hold the batch");
     hipStream_t s = S.streams[k];
     gp_status st = core_ready(c.variant, s);
@@ -182,15 +185,27 @@ static void scheduler(Server* Sp) {
             for (size_t i = 0; i < S.stream_busy.size(); i++)
                 if (!S.stream_busy[i]) { k = (int)i; break; }
             if (k < 0) break;
+            // The oldest request leads the batch (FIFO: if it does not fit the
+            // memory budget, nothing is admitted until memory frees up); later
+            // requests join it if they run with the same kernel variant and fit.
+            // A fused launch runs one variant, so fusing requests that want
+            // different ones would slow all of them to the widest one's.
             std::vector<std::shared_ptr<Request>> take;
             size_t bytes = 0;
-            while (!S.queue.empty() && (int32_t)take.size() < S.cfg.max_batch) {
-                auto& r = S.queue.front();
-                if (r->state == RQ_CANCELLED) { S.queue.pop_front(); continue; }
-                if (S.bytes_in_flight + bytes + r->need > S.cfg.memory_budget) break;  // FIFO: wait for memory
+            int32_t variant = -1;
+            for (auto it = S.queue.begin(); it != S.queue.end() && (int32_t)take.size() < S.cfg.max_batch;) {
+                const std::shared_ptr<Request>& r = *it;
+                if (r->state == RQ_CANCELLED) { it = S.queue.erase(it); continue; }
+                if (!take.empty() && r->variant != variant) { ++it; continue; }
+                if (S.bytes_in_flight + bytes + r->need > S.cfg.memory_budget) {
+                    if (take.empty()) break;
+                    ++it;
+                    continue;
+                }
+                variant = r->variant;
                 bytes += r->need;
                 take.push_back(r);
-                S.queue.pop_front();
+                it = S.queue.erase(it);
             }
             if (take.empty()) break;
             for (auto& r : take) r->state = RQ_RUNNING;
@@ -297,6 +312,13 @@ gp_status gp_serve_submit(gp_server* sv, const gp_job* req, uint64_t* ticket) {
     r->out = req->out;
     r->need = request_bytes(r->pd, ds[req->dataset].n_cases);
     r->gpop = r->pd.n_gpop * ds[req->dataset].n_cases;
+    r->variant = pick_core_variant(r->pd.n_load, r->pd.max_depth,
+                                   r->pd.n_instr ? (double)r->pd.n_exit / (double)r->pd.n_instr : 0.0);
+    if (r->variant < 0 && r->pd.n_prog > 0) {
+        std::lock_guard<std::mutex> g(S.mu);
+        S.n_rejected++;
+        return fail(GP_E_DEPTH, "no kernel variant can hold the request's programs");
+    }
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> g(S.mu);
     if (r->need > S.cfg.memory_budget) {
