@@ -305,6 +305,14 @@ gp_status gp_core_lower_linear(const uint32_t* code, const int64_t* off, const f
 gp_status gp_timing_enable(int on);
 gp_status gp_timing_read(int64_t* launches, double* total_ms, int reset);
 
+/* Launch-shape overrides for tuning and tests, read from the environment at
+ * every one-shot or program-set evaluation: GP2D_GROUP_INSTR (core
+ * instructions per program group), GP2D_TILES_PER_WAVE (case tiles each
+ * wavefront walks per group), GP2D_TARGET_BLOCKS (workgroups the launch aims
+ * for), GP2D_CODE_PREFETCH=0 (no burst load of each program's code into the
+ * scalar cache).  They change the schedule only; fitness values never depend
+ * on them. */
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* gp_last_error(void);
 /* Library version string. */

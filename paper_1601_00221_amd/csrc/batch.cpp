@@ -84,8 +84,6 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
         for (int32_t p = 0; p < pd.n_prog; p++) {
             DevProg dp = jprogs[p];
             dp.code_off += code_base;
-            dp.part_base = part_base + (uint64_t)p;
-            dp.part_stride = (uint32_t)pd.n_prog;
             dp.row = (uint64_t)p;
             plan.progs.push_back(dp);
         }
@@ -121,11 +119,11 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
         jd.ds = j.ds;
         jd.kind = j.kind;
         jd.n_load = pd.n_load;
+        jd.part_base = part_base;
         plan.jobs.push_back(jd);
         ReduceArgs r;
         memset(&r, 0, sizeof r);
         r.part_base = part_base;
-        r.stride = pd.n_prog;
         r.n_prog = pd.n_prog;
         r.N = N;
         r.out = j.out;
@@ -203,6 +201,7 @@ gp_status launch_plan(const BatchPlan& p, BatchScratch& sc, hipStream_t s) {
     a.counter = (uint32_t*)sc.counter.p;
     a.n_units = (int32_t)p.units.size();
     a.persistent = p.persistent ? 1 : 0;
+    a.prefetch = code_prefetch();
     const uint32_t grid = p.persistent ? (uint32_t)(device_cus() * core_blocks_per_cu(p.vi))
                                        : (uint32_t)((p.units.size() + 3) / 4);
     int slot;

@@ -21,6 +21,7 @@ struct JobDesc {
     int32_t kind;
     int32_t n_load;             // features the job's programs read
     int32_t pad;
+    uint64_t part_base;         // the job's partial sums start here (see ReduceArgs)
 };
 
 struct UnitDesc {
@@ -29,10 +30,12 @@ struct UnitDesc {
     uint32_t q0, q1;            // programs order[q0 .. q1)
 };
 
+// Partial sums are program-major: block b of program p (its row in the
+// job) is partials[part_base + p * blocks + b], so one wave's blocks of one
+// program are adjacent.
 struct ReduceArgs {
     const double* partials;
     uint64_t part_base;
-    int64_t stride;             // distance between consecutive blocks of one program
     int64_t n_prog;
     int64_t N;
     void* out;
@@ -49,7 +52,8 @@ struct CoreArgs {
     const JobDesc* jobs;
     const DatasetDesc* datasets;
     uint32_t* counter;          // next unit, persistent form
-    // implicit units: u = (tile u mod tiles, group u div tiles)
+    // implicit units: block unit b = (group b div chunks, chunk b mod chunks);
+    // a chunk is 4 * tiles_per_wave consecutive tiles
     const uint32_t* group_off;
     const float* X;
     const float* y;
@@ -57,8 +61,12 @@ struct CoreArgs {
     int32_t n_load;
     int32_t kind;
     int32_t tiles;
-    int32_t n_units;
+    int32_t n_units;            // table units, or implicit block units
     int32_t persistent;
+    int32_t tiles_per_wave;
+    int32_t chunks;
+    int32_t prefetch;           // burst-load each program's code into the scalar cache first
+    int32_t pad1;
     uint32_t probe;             // nonzero: write the handler table address and return
     double* partials;
     float* cases_out;

@@ -11,9 +11,9 @@
 // sin/cos/exp/log (an exit carries the operand and destination offsets; the
 // kernel moves the T slots out, computes, moves them back) and the end of a
 // program.  sin, cos, exp and log are evaluated in binary64 and rounded
-// once: random GP trees chain many of them, and most such programs turn a
-// last-place difference into a visible fitness difference, so a binary32
-// library result would make fitness depend on the evaluator.
+// once (gp_math.h): random GP trees chain many of them, and most such
+// programs turn a last-place difference into a visible fitness difference,
+// so a binary32 library result would make fitness depend on the evaluator.
 //
 // Fitness: per-slot error terms in binary32, per-lane binary64 sums over the
 // 4 slots of each 256-case block, a fixed wavefront butterfly, one partial
@@ -26,27 +26,12 @@
 #include "../../include/gp.h"
 #include "core_kernels.h"
 #include "gp_internal.h"
+#include "gp_math.h"
 
 namespace gpx {
 #include "core_gen.inc"
 
-template <int N> using fvec_t = float __attribute__((ext_vector_type(N)));
-// Values indexed by a wave-uniform loop counter: with more than 8 elements the
-// compiler selects them with one s_set_gpr_idx move (smaller vectors become
-// compare/select chains).
-template <int T> using ivec_t = fvec_t<(T < 9 ? 9 : T)>;
-
 __device__ __forceinline__ float pdiv(float a, float b) { return (fabsf(b) < 1e-6f) ? 1.0f : a / b; }
-__device__ __forceinline__ float gsin(float a) { return (float)sin((double)a); }
-__device__ __forceinline__ float gcos(float a) { return (float)cos((double)a); }
-__device__ __forceinline__ float expc(float a) {
-    const float t = (a > 88.0f) ? 88.0f : a;  // a NaN fails the compare and passes through
-    return (float)exp((double)t);
-}
-__device__ __forceinline__ float plog(float a) {
-    const float m = fabsf(a);
-    return (m < 1e-6f) ? 0.0f : (float)log((double)m);
-}
 
 // Exit payload: byte 0 offset of A, byte 1 offset of B, byte 2 offset of the
 // destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
@@ -82,30 +67,29 @@ __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
     } else {
         core_gather<T, V0>(oa, A);
     }
-    // one copy of each long function, applied slot by slot
-    ivec_t<T> a;
-#pragma unroll
-    for (int j = 0; j < T; j++) a[j] = A[j];
+    // z is 0, but the compiler cannot know it: the coefficient tables are then
+    // read with scalar loads, once per exit, instead of living in SGPRs
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    // the T slots are independent straight-line evaluations the compiler interleaves
     switch (op) {
         case GP_SIN:
-#pragma unroll 1
-            for (int j = 0; j < T; j++) a[j] = gsin(a[j]);
+#pragma unroll
+            for (int j = 0; j < T; j++) A[j] = gmath::sin32(A[j], z);
             break;
         case GP_COS:
-#pragma unroll 1
-            for (int j = 0; j < T; j++) a[j] = gcos(a[j]);
+#pragma unroll
+            for (int j = 0; j < T; j++) A[j] = gmath::cos32(A[j], z);
             break;
         case GP_EXPC:
-#pragma unroll 1
-            for (int j = 0; j < T; j++) a[j] = expc(a[j]);
+#pragma unroll
+            for (int j = 0; j < T; j++) A[j] = gmath::expc32(A[j], z);
             break;
         default:  // GP_PLOG
-#pragma unroll 1
-            for (int j = 0; j < T; j++) a[j] = plog(a[j]);
+#pragma unroll
+            for (int j = 0; j < T; j++) A[j] = gmath::plog32(A[j], z);
             break;
     }
-#pragma unroll
-    for (int j = 0; j < T; j++) A[j] = a[j];
     core_scatter<T, V0>(od, A);
 }
 
@@ -120,8 +104,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // mode the core only reports where its handler table starts.
 template <int T, int D, int NF, int V0>
 __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, const float* y, int64_t N,
-                                             int32_t n_load, int32_t kind, uint32_t tile, uint32_t q0,
-                                             uint32_t q1) {
+                                             int32_t n_load, int32_t kind, uint64_t pbase, uint32_t tile,
+                                             uint32_t q0, uint32_t q1) {
     static_assert(T % 4 == 0, "a tile holds whole 256-case blocks");
     constexpr int RB = D > GPX_LIN_REGS ? D : GPX_LIN_REGS;   // register/stack levels before the features
     const uint32_t lane = threadIdx.x & 63u;
@@ -145,10 +129,13 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             // program records are wave-uniform; keep the core's offset in an SGPR
             off = __builtin_amdgcn_readfirstlane(P.code_off) * 4u;
         }
+        // first entry: burst the program's code into the scalar cache
+        uint32_t pf_end = (a.probe || !a.prefetch) ? 0u : off + __builtin_amdgcn_readfirstlane(P.len) * 16u;
         for (;;) {
             uint32_t pay, cst;
             uint64_t table;
-            Core<T, D, NF, V0>::run(code, off, pay, cst, a.probe, table);
+            Core<T, D, NF, V0>::run(code, off, pay, cst, a.probe, pf_end, table);
+            pf_end = 0u;
             if (a.probe) {
                 if (threadIdx.x == 0) a.probe_out[0] = table;
                 return;
@@ -168,9 +155,9 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             continue;
         }
         const float* yt = y + tile0;
+        double mine = 0.0;   // lane k keeps block k's partial
 #pragma unroll
         for (int k = 0; k < T / 4; k++) {
-            const int64_t blk = (int64_t)tile * (T / 4) + k;
             double v;
             if (kind == GP_FIT_HITS) {
                 uint32_t hits = 0;
@@ -194,39 +181,53 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
                 }
                 v = wave_sum(acc);
             }
-            if (lane == 0 && blk < n_blocks) a.partials[P.part_base + (uint64_t)blk * P.part_stride] = v;
+            if (lane == (uint32_t)k) mine = v;
         }
+        // the tile's T/4 blocks of this program are adjacent: one store
+        const int64_t blk = (int64_t)tile * (T / 4) + lane;
+        if (lane < (uint32_t)(T / 4) && blk < n_blocks) a.partials[pbase + P.row * (uint64_t)n_blocks + blk] = mine;
     }
 }
 
 // Units come either from a table (batched launches: persistent waves pull
-// them longest first from a counter, or one wave per unit) or implicitly,
-// unit u = (tile u mod tiles, program group u div tiles) over one dataset.
+// them longest first from a counter, or one wave per unit) or implicitly
+// over one dataset: block unit b = (program group b div chunks, chunk b mod
+// chunks), and wave w of the block runs the group on tiles
+// (chunk * tiles_per_wave + i) * 4 + w, i = 0 .. tiles_per_wave - 1.  The
+// four waves of a block walk the same instruction stream side by side and
+// each walks it again for its next tile, so a group small enough for the
+// scalar cache is fetched from L2 once per block rather than once per tile.
 template <int T, int D, int NF, int V0>
 __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool table = a.units != nullptr;
-    uint32_t u;
+    uint32_t u, grp = 0, chunk = 0;
     if (table) {
         u = blockIdx.x * 4u + wib;
     } else {
         // Blocks go to the 8 XCDs round robin; give each XCD a contiguous
-        // range of units so a program group's code stays in one L2.
+        // range of block units so a program group's code stays in one L2.
         const uint32_t nb = gridDim.x, b = blockIdx.x;
-        u = ((b & 7u) * (nb >> 3) + (b >> 3)) * 4u + wib;
+        u = (b & 7u) * (nb >> 3) + (b >> 3);
+        if (!a.probe) {
+            if (u >= (uint32_t)a.n_units) return;
+            grp = u / (uint32_t)a.chunks;
+            chunk = u % (uint32_t)a.chunks;
+        }
     }
-    for (;;) {
+    for (uint32_t it = 0;; ++it) {
         uint32_t tile = 0, q0 = 0, q1 = 1;
+        uint64_t pbase = 0;
         const float *X = nullptr, *y = nullptr;
         int64_t N = 1;
         int32_t n_load = 0, kind = 0;
         if (a.probe) {
-            if (u != 0) return;
+            if (u != 0 || wib != 0) return;
         } else if (!table) {
-            if (u >= (uint32_t)a.n_units) return;
-            tile = u % (uint32_t)a.tiles;
-            const uint32_t grp = u / (uint32_t)a.tiles;
+            if (it >= (uint32_t)a.tiles_per_wave) return;
+            tile = (chunk * (uint32_t)a.tiles_per_wave + it) * 4u + wib;
+            if (tile >= (uint32_t)a.tiles) return;
             q0 = a.group_off[grp];
             q1 = a.group_off[grp + 1];
             X = a.X;
@@ -239,6 +240,8 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
                 uint32_t t = 0;
                 if (lane == 0) t = atomicAdd(a.counter, 1u);
                 u = __builtin_amdgcn_readfirstlane(t);
+            } else if (it > 0) {
+                return;
             }
             if (u >= (uint32_t)a.n_units) return;
             const UnitDesc ud = a.units[u];
@@ -252,10 +255,11 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
             N = dd.N;
             n_load = jd.n_load;
             kind = jd.kind;
+            pbase = jd.part_base;
         }
-        process_unit<T, D, NF, V0>(a, X, y, N, n_load, kind, __builtin_amdgcn_readfirstlane(tile),
+        process_unit<T, D, NF, V0>(a, X, y, N, n_load, kind, pbase, __builtin_amdgcn_readfirstlane(tile),
                                __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1));
-        if (a.probe || !table || !a.persistent) return;
+        if (a.probe) return;
     }
 }
 
@@ -278,9 +282,9 @@ __global__ __launch_bounds__(256) void k_reduce_jobs(const ReduceArgs* jobs) {
     const ReduceArgs r = jobs[blockIdx.y];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= r.n_prog) return;
-    const double* src = r.partials + r.part_base + p;
+    const double* src = r.partials + r.part_base + p * (int64_t)r.blocks;
     double s = 0.0;
-    for (int32_t t = 0; t < r.blocks; t++) s += src[(int64_t)t * r.stride];
+    for (int32_t t = 0; t < r.blocks; t++) s += src[t];
     if (r.kind == GP_FIT_HITS) ((int32_t*)r.out)[p] = (int32_t)s;
     else if (r.kind == GP_FIT_MSE) ((float*)r.out)[p] = (float)(s / (double)r.N);
     else ((float*)r.out)[p] = (float)s;
@@ -289,9 +293,9 @@ __global__ __launch_bounds__(256) void k_reduce_jobs(const ReduceArgs* jobs) {
 __global__ __launch_bounds__(256) void k_reduce_one(ReduceArgs r) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= r.n_prog) return;
-    const double* src = r.partials + r.part_base + p;
+    const double* src = r.partials + r.part_base + p * (int64_t)r.blocks;
     double s = 0.0;
-    for (int32_t t = 0; t < r.blocks; t++) s += src[(int64_t)t * r.stride];
+    for (int32_t t = 0; t < r.blocks; t++) s += src[t];
     if (r.kind == GP_FIT_HITS) ((int32_t*)r.out)[p] = (int32_t)s;
     else if (r.kind == GP_FIT_MSE) ((float*)r.out)[p] = (float)(s / (double)r.N);
     else ((float*)r.out)[p] = (float)s;

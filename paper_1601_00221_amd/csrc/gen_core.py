@@ -94,10 +94,19 @@ def gen_variant(T, D, NF, NCV):
     tag = "T%dD%dF%dV%d" % (T, D, NF, NCV)
     hs = []
 
-    def prologue(h, const=False, second_index=False):
+    def prologue(h, const=False, second_index=False, index=None):
+        """Save what the handler still needs from the current record (the
+        next record's load overwrites s[64:67]), then start that load.  A
+        handler with one index turns the index mode on straight from the
+        payload, before the load is issued."""
         if const:
             h.emit("s_mov_b32 s72, s67", 4)
-        h.emit("s_mov_b32 s70, s66", 4)
+        if index == "off":
+            h.emit("s_set_gpr_idx_off", 4)
+        elif index is not None:
+            idx_on(h, "s66", index)
+        else:
+            h.emit("s_mov_b32 s70, s66", 4)
         if second_index:
             h.emit("s_lshr_b32 s71, s66, 8", 4)
         h.emit("s_add_u32 s62, s62, 16", 4)
@@ -122,15 +131,13 @@ def gen_variant(T, D, NF, NCV):
     # ---------------------------------------------------------------- trees
     for op in ("add", "sub", "mul"):
         h = Handler(K["SS"], OP_ID[op])            # s[h-2] = s[h-2] op s[h-1]; index (h-2)*T
-        prologue(h)
-        idx_on(h, "s70", ["SRC0", "SRC1", "DST"])
+        prologue(h, index=["SRC0", "SRC1", "DST"])
         for j in range(T):
             valu(h, "%s %s, %s, %s" % (OPS[op], vr(V0 + j), vr(V0 + j), vr(V0 + T + j)))
         epilogue(h)
         hs.append(h)
     h = Handler(K["SSR"], OP_ID["sub"])            # s[h-2] = s[h-1] - s[h-2]
-    prologue(h)
-    idx_on(h, "s70", ["SRC0", "SRC1", "DST"])
+    prologue(h, index=["SRC0", "SRC1", "DST"])
     for j in range(T):
         valu(h, "v_sub_f32_e32 %s, %s, %s" % (vr(V0 + j), vr(V0 + T + j), vr(V0 + j)))
     epilogue(h)
@@ -138,8 +145,7 @@ def gen_variant(T, D, NF, NCV):
     for op in ("add", "sub", "mul"):
         for l in range(D):
             h = Handler(K["SX"], OP_ID[op], l)     # s[l] = s[l] op x[b]; index = feature offset
-            prologue(h)
-            idx_on(h, "s70", ["SRC1"])
+            prologue(h, index=["SRC1"])
             for j in range(T):
                 r = vr(V0 + l * T + j)
                 valu(h, "%s %s, %s, %s" % (OPS[op], r, r, vr(V0 + j)))
@@ -147,8 +153,7 @@ def gen_variant(T, D, NF, NCV):
             hs.append(h)
     for l in range(D):
         h = Handler(K["XS"], OP_ID["sub"], l)      # s[l] = x[a] - s[l]
-        prologue(h)
-        idx_on(h, "s70", ["SRC0"])
+        prologue(h, index=["SRC0"])
         for j in range(T):
             r = vr(V0 + l * T + j)
             valu(h, "v_sub_f32_e32 %s, %s, %s" % (r, vr(V0 + j), r))
@@ -156,15 +161,13 @@ def gen_variant(T, D, NF, NCV):
         hs.append(h)
     for op, ins in (("add", "v_add_f32_e32"), ("mul", "v_mul_f32_e32"), ("sub", "v_subrev_f32_e32")):
         h = Handler(K["SC"], OP_ID[op])            # s[l] = s[l] op c; index l*T
-        prologue(h, const=True)
-        idx_on(h, "s70", ["SRC1", "DST"])
+        prologue(h, const=True, index=["SRC1", "DST"])
         for j in range(T):
             valu(h, "%s %s, s72, %s" % (ins, vr(V0 + j), vr(V0 + j)))
         epilogue(h)
         hs.append(h)
     h = Handler(K["CS"], OP_ID["sub"])             # s[l] = c - s[l]
-    prologue(h, const=True)
-    idx_on(h, "s70", ["SRC1", "DST"])
+    prologue(h, const=True, index=["SRC1", "DST"])
     for j in range(T):
         valu(h, "v_sub_f32_e32 %s, s72, %s" % (vr(V0 + j), vr(V0 + j)))
     epilogue(h)
@@ -177,8 +180,7 @@ def gen_variant(T, D, NF, NCV):
             for l in range(D):
                 for dl in deltas:
                     h = Handler(K["XX"], OP_ID[op], l, dl)
-                    prologue(h)
-                    idx_on(h, "s70", ["SRC0", "SRC1"])
+                    prologue(h, index=["SRC0", "SRC1"])
                     for j in range(T):
                         valu(h, "%s %s, %s, %s" % (OPS[op], vr(V0 + l * T + j), vr(V0 + FO + j),
                                                    vr(V0 + FO + dl * T + j)))
@@ -200,30 +202,26 @@ def gen_variant(T, D, NF, NCV):
     for op, ins in (("add", "v_add_f32_e32"), ("mul", "v_mul_f32_e32"), ("sub", "v_subrev_f32_e32")):
         for l in range(D):
             h = Handler(K["XC"], OP_ID[op], l)     # push x[a] op c
-            prologue(h, const=True)
-            idx_on(h, "s70", ["SRC1"])
+            prologue(h, const=True, index=["SRC1"])
             for j in range(T):
                 valu(h, "%s %s, s72, %s" % (ins, vr(V0 + l * T + j), vr(V0 + j)))
             epilogue(h)
             hs.append(h)
     for l in range(D):
         h = Handler(K["CX"], OP_ID["sub"], l)      # push c - x[b]
-        prologue(h, const=True)
-        idx_on(h, "s70", ["SRC1"])
+        prologue(h, const=True, index=["SRC1"])
         for j in range(T):
             valu(h, "v_sub_f32_e32 %s, s72, %s" % (vr(V0 + l * T + j), vr(V0 + j)))
         epilogue(h)
         hs.append(h)
     h = Handler(K["PUSHX"])                        # s[0] = x[a] (a program that is one variable)
-    prologue(h)
-    idx_on(h, "s70", ["SRC0"])
+    prologue(h, index=["SRC0"])
     for j in range(T):
         valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + j), vr(V0 + j)))
     epilogue(h)
     hs.append(h)
     h = Handler(K["PUSHC"])                        # s[l] = c; index l*T
-    prologue(h, const=True)
-    idx_on(h, "s70", ["DST"])
+    prologue(h, const=True, index=["DST"])
     for j in range(T):
         valu(h, "v_mov_b32_e32 %s, s72" % vr(V0 + j))
     epilogue(h)
@@ -235,8 +233,7 @@ def gen_variant(T, D, NF, NCV):
         for d in range(R):
             for s1 in range(R):
                 h = Handler(K["RR"], OP_ID[op], d, s1)   # r[d] = r[s1] op src2 (index)
-                prologue(h)
-                idx_on(h, "s70", ["SRC1"])
+                prologue(h, index=["SRC1"])
                 for j in range(T):
                     valu(h, "%s %s, %s, %s" % (OPS[op], vr(V0 + d * T + j), vr(V0 + s1 * T + j), vr(V0 + j)))
                 epilogue(h)
@@ -244,8 +241,7 @@ def gen_variant(T, D, NF, NCV):
     for d in range(R):
         for s2 in range(R):
             h = Handler(K["XR"], OP_ID["sub"], d, s2)    # r[d] = src1 (index) - r[s2]
-            prologue(h)
-            idx_on(h, "s70", ["SRC0"])
+            prologue(h, index=["SRC0"])
             for j in range(T):
                 valu(h, "v_sub_f32_e32 %s, %s, %s" % (vr(V0 + d * T + j), vr(V0 + j), vr(V0 + s2 * T + j)))
             epilogue(h)
@@ -266,32 +262,28 @@ def gen_variant(T, D, NF, NCV):
     for op in ("add", "sub", "mul"):
         for d in range(R):
             h = Handler(K["CR"], OP_ID[op], d)           # r[d] = c op src (index)
-            prologue(h, const=True)
-            idx_on(h, "s70", ["SRC1"])
+            prologue(h, const=True, index=["SRC1"])
             for j in range(T):
                 valu(h, "%s %s, s72, %s" % (OPS[op], vr(V0 + d * T + j), vr(V0 + j)))
             epilogue(h)
             hs.append(h)
     for d in range(R):
         h = Handler(K["RC"], OP_ID["sub"], d)            # r[d] = src (index) - c
-        prologue(h, const=True)
-        idx_on(h, "s70", ["SRC1"])
+        prologue(h, const=True, index=["SRC1"])
         for j in range(T):
             valu(h, "v_subrev_f32_e32 %s, s72, %s" % (vr(V0 + d * T + j), vr(V0 + j)))
         epilogue(h)
         hs.append(h)
     for d in range(R):
         h = Handler(K["MOVC"], 0, d)                     # r[d] = c
-        prologue(h, const=True)
-        h.emit("s_set_gpr_idx_off", 4)
+        prologue(h, const=True, index="off")
         for j in range(T):
             valu(h, "v_mov_b32_e32 %s, s72" % vr(V0 + d * T + j))
         epilogue(h)
         hs.append(h)
     for d in range(R):
         h = Handler(K["MOVX"], 0, d)                     # r[d] = src (index)
-        prologue(h)
-        idx_on(h, "s70", ["SRC0"])
+        prologue(h, index=["SRC0"])
         for j in range(T):
             valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + d * T + j), vr(V0 + j)))
         epilogue(h)
@@ -315,6 +307,24 @@ def asm_text(T, D, NF, tag, hs):
     L.append("s_addc_u32 s77, s77, 0")
     L.append("s_branch .Lgpx_end_%s" % tag)
     L.append(".Lgpx_run_%s:" % tag)
+    # Burst-load the program's remaining 64-byte lines (from the current
+    # record's line up to byte offset s68) into the scalar cache, up to 8
+    # loads in flight, so the handlers' one-record-ahead loads then hit.
+    # s68 = 0 skips it (re-entry after an exit).  s69 only receives data.
+    L.append("s_and_b32 s73, s62, 0xffffffc0")
+    L.append("s_mov_b32 s74, 0")
+    L.append(".Lgpx_pf_%s:" % tag)
+    L.append("s_cmp_lt_u32 s73, s68")
+    L.append("s_cbranch_scc0 .Lgpx_pfdone_%s" % tag)
+    L.append("s_load_dword s69, s[60:61], s73")
+    L.append("s_add_u32 s73, s73, 64")
+    L.append("s_add_u32 s74, s74, 1")
+    L.append("s_cmp_lt_u32 s74, 8")
+    L.append("s_cbranch_scc1 .Lgpx_pf_%s" % tag)
+    L.append("s_waitcnt lgkmcnt(0)")
+    L.append("s_mov_b32 s74, 0")
+    L.append("s_branch .Lgpx_pf_%s" % tag)
+    L.append(".Lgpx_pfdone_%s:" % tag)
     L.append("s_load_dwordx4 s[64:67], s[60:61], s62")
     L.append("s_waitcnt lgkmcnt(0)")
     L.append("s_setpc_b64 s[64:65]")
@@ -383,13 +393,16 @@ def main(out_dir):
         assert NCV + FO + NF * T <= 256
         lines.append("template <> struct Core<%d, %d, %d, %d> {" % (T, D, NF, NCV))
         lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")
+        lines.append("    // pf_end: byte offset where the program ends (its code is first burst-loaded into the")
+        lines.append("    // scalar cache), or 0")
         lines.append("    static __device__ __forceinline__ void run(uint64_t base, uint32_t& off, uint32_t& pay,"
-                     " uint32_t& cst, uint32_t probe, uint64_t& table) {")
+                     " uint32_t& cst, uint32_t probe, uint32_t pf_end, uint64_t& table) {")
         lines.append("#ifdef __HIP_DEVICE_COMPILE__")
         lines.append('        asm volatile("%s"' % text)
         lines.append('            : "+{s62}"(off), "={s66}"(pay), "={s67}"(cst), "={s[76:77]}"(table)')
-        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe)')
-        lines.append('            : %s, "s64", "s65", "s70", "s71", "s72", "scc", "m0", "memory");' % clob_v)
+        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe), "{s68}"(pf_end)')
+        lines.append('            : %s, "s64", "s65", "s69", "s70", "s71", "s72", "s73", "s74", "scc", "m0", "memory");'
+                     % clob_v)
         lines.append("#endif")
         lines.append("    }")
         lines.append("};")

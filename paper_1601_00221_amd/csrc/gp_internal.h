@@ -50,8 +50,8 @@ struct DevProg {
     uint32_t len;          // instructions (trees: 2 words each; linear: 1 word each,
                            //   followed by the program's constants)
     uint32_t meta;         // bit 0 form; bits 8-15 stack depth (tree) or n_reg (linear)
-    uint32_t part_stride;  // distance between the partial sums of consecutive tiles
-    uint64_t part_base;    // partial sum of tile t is at part_base + t * part_stride
+    uint32_t reserved0;
+    uint64_t reserved1;
     uint64_t row;          // program index within its population (per-case output row)
 };
 static_assert(sizeof(DevProg) == 32, "DevProg layout");

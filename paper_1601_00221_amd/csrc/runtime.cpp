@@ -3,6 +3,7 @@
 // the C ABI declared in include/gp.h.
 #include <hip/hip_runtime_api.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -177,8 +178,8 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
         d.code_off = (uint32_t)(2 * w);
         d.len = (uint32_t)st.n_instr;
         d.meta = FORM_TREE | ((uint32_t)st.max_depth << 8);
-        d.part_stride = (uint32_t)P;
-        d.part_base = (uint64_t)p;
+        d.reserved0 = 0;
+        d.reserved1 = 0;
         d.row = (uint64_t)p;
         pd.cost[p] = cost + 8;
         pd.max_depth = std::max(pd.max_depth, st.max_depth);
@@ -247,8 +248,8 @@ gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cs
         d.code_off = (uint32_t)w;
         d.len = (uint32_t)n;
         d.meta = FORM_LINEAR | ((uint32_t)n_reg << 8);
-        d.part_stride = (uint32_t)P;
-        d.part_base = (uint64_t)p;
+        d.reserved0 = 0;
+        d.reserved1 = 0;
         d.row = (uint64_t)p;
         pd.cost[p] = cost + 8;
         pd.n_instr += n;
@@ -316,13 +317,47 @@ static gp_status groups_for(const ProgData& pd, DevProgs& dp, int32_t G, hipStre
     return GP_OK;
 }
 
-// Number of program groups: enough (tile, group) units to keep every
-// wavefront slot of the chip busy several times over.
-static int32_t choose_groups(int32_t P, int32_t tiles, int32_t target_units) {
-    int64_t g = (target_units + (int64_t)tiles - 1) / tiles;
-    if (g < 1) g = 1;
-    if (g > P) g = P;
-    return (int32_t)g;
+// Launch shape of one evaluation.  Programs are dealt into G groups of
+// about `group_instr` core instructions (small enough that a block's group
+// stays in the scalar cache while its waves walk it tile after tile); each
+// block runs one group on a chunk of 4 * tiles_per_wave tiles.  The chunk is
+// as long as still leaves `target_blocks` blocks; with few tiles, groups are
+// made smaller instead, down to one program, so the chip still fills.
+struct LaunchShape {
+    int32_t G, tiles_per_wave, chunks;
+};
+
+static int32_t env_int(const char* name, int32_t dflt) {
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    const long x = strtol(v, nullptr, 10);
+    return x > 0 && x < (1L << 30) ? (int32_t)x : dflt;
+}
+
+// Burst-load each program's code into the scalar cache before running it
+// (GP2D_CODE_PREFETCH=0 turns it off, for measurement).
+int32_t code_prefetch() {
+    const char* v = getenv("GP2D_CODE_PREFETCH");
+    return (v && v[0] == '0') ? 0 : 1;
+}
+
+static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOptions* opt) {
+    const int32_t group_instr = opt && opt->group_instr > 0 ? opt->group_instr : env_int("GP2D_GROUP_INSTR", 4096);
+    const int32_t target_blocks = opt && opt->target_blocks > 0 ? opt->target_blocks : env_int("GP2D_TARGET_BLOCKS", 4096);
+    const int64_t quads = (tiles + 3) / 4;
+    int64_t G = (pd.n_instr + group_instr - 1) / group_instr;
+    if (G * quads < target_blocks) G = (target_blocks + quads - 1) / quads;
+    G = std::max<int64_t>(1, std::min<int64_t>(G, pd.n_prog));
+    int32_t tpw = opt && opt->tiles_per_wave > 0 ? opt->tiles_per_wave : env_int("GP2D_TILES_PER_WAVE", 0);
+    if (tpw <= 0) {
+        tpw = 1;
+        while (tpw < 16 && G * ((quads + 2 * tpw - 1) / (2 * tpw)) >= target_blocks) tpw *= 2;
+    }
+    LaunchShape L;
+    L.G = (int32_t)G;
+    L.tiles_per_wave = tpw;
+    L.chunks = (int32_t)((quads + tpw - 1) / tpw);
+    return L;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,9 +423,9 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     const int64_t tiles64 = (N + 64LL * T - 1) / (64LL * T);
     if (tiles64 > (1LL << 30)) return fail(GP_E_INVAL, "n_cases too large");
     const int32_t tiles = (int32_t)tiles64;
-    const int32_t target = opt && opt->target_units > 0 ? opt->target_units : 16384;
-    const int32_t G = opt && opt->groups > 0 ? std::min(opt->groups, pd.n_prog) : choose_groups(pd.n_prog, tiles, target);
-    const int64_t units = (int64_t)tiles * G;
+    const LaunchShape L = launch_shape(pd, tiles, opt);
+    const int32_t G = L.G;
+    const int64_t units = (int64_t)L.chunks * G;
     if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
     const uint32_t *order, *goff;
     if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
@@ -411,9 +446,12 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     a.kind = kind;
     a.tiles = tiles;
     a.n_units = (int32_t)units;
+    a.tiles_per_wave = L.tiles_per_wave;
+    a.chunks = L.chunks;
+    a.prefetch = code_prefetch();
     a.partials = (double*)w.partials.p;
     a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
-    uint32_t blocks = (uint32_t)((units + 3) / 4);
+    uint32_t blocks = (uint32_t)units;
     blocks = (blocks + 7u) & ~7u;
     int slot;
     hipError_t e = timed_launch_begin(s, &slot);
@@ -425,7 +463,6 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     memset(&r, 0, sizeof r);
     r.partials = (const double*)w.partials.p;
     r.part_base = 0;
-    r.stride = pd.n_prog;
     r.n_prog = pd.n_prog;
     r.N = N;
     r.out = out;

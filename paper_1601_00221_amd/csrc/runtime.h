@@ -82,12 +82,14 @@ struct Workspace {
 };
 
 struct EvalOptions {
-    int variant = -1;        // core variant index, -1 = widest tile that fits
-    int32_t groups = 0;      // program groups, 0 = automatic
-    int32_t target_units = 0;
+    int variant = -1;            // core variant index, -1 = chosen from the programs
+    int32_t group_instr = 0;     // core instructions per program group, 0 = automatic
+    int32_t tiles_per_wave = 0;  // tiles each wave walks per group, 0 = automatic
+    int32_t target_blocks = 0;   // blocks the launch should have at least, 0 = automatic
 };
 
 Workspace& workspace(hipStream_t s);
+int32_t code_prefetch();
 
 // Kernel timing brackets (active only while gp_timing_enable(1)).
 hipError_t timed_launch_begin(hipStream_t s, int* slot);

@@ -1,0 +1,17 @@
+// Host build of the evaluator's binary32 transcendentals (gp_math.h), for
+// testing them against the oracle on the CPU.
+#include <stdint.h>
+
+#include "gp_math.h"
+
+extern "C" void gm_eval(int op, const float* in, float* out, int64_t n) {
+    for (int64_t i = 0; i < n; i++) {
+        const float a = in[i];
+        switch (op) {
+            case 4: out[i] = gpx::gmath::sin32(a); break;
+            case 5: out[i] = gpx::gmath::cos32(a); break;
+            case 6: out[i] = gpx::gmath::expc32(a); break;
+            default: out[i] = gpx::gmath::plog32(a); break;
+        }
+    }
+}

@@ -310,3 +310,46 @@ def test_full_linear_workload_sampled():
     ref = oracle.eval_linear(sub.code, sub.off, sub.cst, sub.cst_off, 8, w.X, w.y, "hits", threads=8)
     assert np.array_equal(got[sample], ref)
     assert np.all((got >= 0) & (got <= w.X.shape[1]))
+
+
+# --------------------------------------------------------------------------
+# Launch shapes: the program grouping and the number of tiles each wave
+# walks change the schedule only, never a result
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["tree", "linear"])
+def test_launch_shapes_give_identical_results(form, monkeypatch):
+    import torch
+    rng = synth.rng_for(31)
+    F = 8
+    if form == "tree":
+        pop = synth.ptc2_population(rng, 150, synth.FULL, F, 1, 120, 1 / 9)
+    else:
+        pop = synth.linear_population(rng, 150, 1, 120, synth.BASIC, 8, F, n_const=2)
+    # 14 tiles of 512 cases and a ragged last one: chunks of 4 * tiles_per_wave
+    # tiles do not divide it for most shapes
+    N = 512 * 13 + 301
+    X = synth.uniform_cases(rng, F, N, -3, 3)
+    y = synth.gaussian_noise(rng, N, 1.0)
+    kind = "mse"
+    ref = None
+    # (core instructions per group, tiles per wave, blocks the launch aims for)
+    for gi, tpw, tb in ((0, 0, 0), (1, 1, 1), (7, 3, 1), (40, 2, 1), (100000, 16, 1), (100000, 1, 1),
+                        (192, 5, 1), (192, 0, 4096)):
+        if gi:
+            monkeypatch.setenv("GP2D_GROUP_INSTR", str(gi))
+            monkeypatch.setenv("GP2D_TARGET_BLOCKS", str(tb))
+            if tpw:
+                monkeypatch.setenv("GP2D_TILES_PER_WAVE", str(tpw))
+            else:
+                monkeypatch.delenv("GP2D_TILES_PER_WAVE", raising=False)
+        say("launch shape %s group_instr=%d tiles_per_wave=%d target_blocks=%d" % (form, gi, tpw, tb))
+        got = gpu_tree(pop, X, y, kind) if form == "tree" else gpu_linear(pop, X, y, kind)
+        cases = gpu_tree(pop, X, None, "cases") if form == "tree" else gpu_linear(pop, X, None, "cases")
+        if ref is None:
+            ref, ref_cases = got, cases
+            want = (oracle.tree_outputs(pop.tok, pop.cst, pop.off, X) if form == "tree" else
+                    oracle.linear_outputs(pop.code, pop.off, pop.cst, pop.cst_off, pop.n_reg, X))
+            assert same_bits(cases, want).mean() >= 0.9999
+        assert np.array_equal(got.view(np.int32), ref.view(np.int32))
+        assert same_bits(cases, ref_cases).all()
+    torch.cuda.synchronize()
