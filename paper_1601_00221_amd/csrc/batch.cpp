@@ -34,10 +34,10 @@ static int device_cus() {
     return cus;
 }
 
-static double exit_fraction(const std::vector<BatchJobRef>& jobs) {
+static double transc_fraction(const std::vector<BatchJobRef>& jobs) {
     int64_t e = 0, n = 0;
     for (const BatchJobRef& j : jobs) {
-        e += j.pd->n_exit;
+        e += j.pd->n_transc;
         n += j.pd->n_instr;
     }
     return n ? (double)e / (double)n : 0.0;
@@ -379,7 +379,7 @@ gp_batch_config default_config(const std::vector<BatchJobRef>& jobs) {
     }
     gp_batch_config c;
     memset(&c, 0, sizeof c);
-    c.variant = pick_core_variant(n_load, depth, exit_fraction(jobs));
+    c.variant = pick_core_variant(n_load, depth, transc_fraction(jobs));
     c.unit_programs = 32;
     c.persistent = 1;
     return c;

@@ -41,16 +41,22 @@ const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
 int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
 int core_reg_levels(int vi) { return kCoreVariants[vi].d > GPX_LIN_REGS ? kCoreVariants[vi].d : GPX_LIN_REGS; }
 
-int pick_core_variant(int n_load, int depth, double exit_frac) {
-    // Programs where many instructions leave the core (binary64 transcendentals,
-    // protected division) want room for the compiled code that does that work;
-    // arithmetic programs want more waves.  Then the widest tile, then the
-    // fewest handlers (least code).
-    const bool heavy = exit_frac > 0.2;
+int pick_core_variant(int n_load, int depth, double transc_frac) {
+    // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
+    // outside the core) run best with room for that code (no spills) and as
+    // many waves per SIMD as that leaves, to hide its latency; the others with
+    // the widest tile.  Ties go to the fewest feature slots, then the fewest
+    // handlers (least code).  (Measured on the 4096 x 65,536 tree workloads.)
+    const bool heavy = transc_frac > 0.2;
     int best = -1;
+    auto waves = [](const CoreVariantDesc& v) {
+        const int lv = v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
+        const int vg = (v.ncv + lv * v.t + v.nf * v.t + 7) / 8 * 8;
+        return 512 / vg;
+    };
     auto score = [&](const CoreVariantDesc& v) {
-        const int fit = heavy ? (v.ncv >= 80) : (v.ncv <= 64);
-        return fit * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
+        if (heavy) return (v.ncv >= 64) * 100000000 + waves(v) * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
+        return (v.ncv <= 64) * 100000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
     };
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];

@@ -19,8 +19,8 @@ int core_variant_nf(int vi);       // feature slots
 int core_variant_ncv(int vi);      // VGPRs left to the compiled code
 int core_reg_levels(int vi);       // register/stack levels before the features
 // Variant for programs reading n_load features, needing `depth` stack levels,
-// with a fraction exit_frac of instructions leaving the core; -1 if none fits.
-int pick_core_variant(int n_load, int depth, double exit_frac);
+// with a fraction transc_frac of sin/cos/exp/log instructions; -1 if none fits.
+int pick_core_variant(int n_load, int depth, double transc_frac);
 // Locate the variant's handler table on the current device (one probe launch
 // on stream s the first time).
 gp_status core_ready(int vi, hipStream_t s);

@@ -58,6 +58,9 @@ VARIANTS = [
     (8, 8, 8, 128),
     (4, 8, 16, 128),
     (4, 12, 32, 80),
+    (4, 8, 8, 64),
+    (4, 8, 8, 96),
+    (4, 8, 16, 64),
 ]
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
@@ -422,12 +425,50 @@ def main(out_dir):
         lines.append("    {%d, %d, %d, %d, kCoreKeys_%s, kCoreSlots_%s, %d, %d}," % (T, D, NF, NCV, tag, tag, len(hs), nslots * SLOT))
     lines.append("};")
     path = os.path.join(out_dir, "core_gen.inc")
-    with open(path + ".tmp", "w") as f:
-        f.write("\n".join(lines) + "\n")
-    os.replace(path + ".tmp", path)
+    write_if_changed(path, "\n".join(lines) + "\n")
+    # one translation unit per kernel variant, and the launch table
+    disp = ["// Generated by gen_core.py -- do not edit.", "#pragma once", "",
+            "typedef hipError_t (*CoreLaunchFn)(const CoreArgs&, uint32_t, hipStream_t);",
+            "typedef int (*CoreOccupancyFn)();"]
+    for (T, D, NF, NCV, tag, hs, nslots) in host:
+        name = "%d_%d_%d_%d" % (T, D, NF, NCV)
+        disp.append("hipError_t core_launch_%s(const CoreArgs& a, uint32_t blocks, hipStream_t s);" % name)
+        disp.append("int core_occupancy_%s();" % name)
+        tu = ["// Generated by gen_core.py -- do not edit.  Kernel variant %s." % tag,
+              '#include "core_body.h"', "", "namespace gpx {",
+              "GPX_KERNEL(%d, %d, %d, %d)" % (T, D, NF, NCV), "",
+              "hipError_t core_launch_%s(const CoreArgs& a, uint32_t blocks, hipStream_t s) {" % name,
+              "    hipLaunchKernelGGL(k_core_%s, dim3(blocks), dim3(256), 0, s, a);" % name,
+              "    return hipGetLastError();", "}", "",
+              "int core_occupancy_%s() {" % name,
+              "    int n = 0;",
+              "    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_core_%s, 256, 0) != hipSuccess) n = 1;" % name,
+              "    return n;", "}", "}  // namespace gpx", ""]
+        write_if_changed(os.path.join(out_dir, "core_v_%s.hip" % name), "\n".join(tu))
+    names = ["%d_%d_%d_%d" % (T, D, NF, NCV) for (T, D, NF, NCV, tag, hs, nslots) in host]
+    disp.append("static const CoreLaunchFn kCoreLaunch[] = {%s};" % ", ".join("core_launch_" + n for n in names))
+    disp.append("static const CoreOccupancyFn kCoreOccupancy[] = {%s};"
+                % ", ".join("core_occupancy_" + n for n in names))
+    write_if_changed(os.path.join(out_dir, "core_dispatch.inc"), "\n".join(disp) + "\n")
     for (T, D, NF, NCV, tag, hs, nslots) in host:
         print("%s: %d handlers, %d slots (%d KiB)" % (tag, len(hs), nslots, nslots * SLOT // 1024))
     return path
+
+
+def variant_sources():
+    """File names of the generated per-variant translation units."""
+    return ["core_v_%d_%d_%d_%d.hip" % v for v in VARIANTS]
+
+
+def write_if_changed(path, text):
+    """Write text unless the file already holds it (keeps mtimes for incremental builds)."""
+    if os.path.exists(path):
+        with open(path) as f:
+            if f.read() == text:
+                return
+    with open(path + ".tmp", "w") as f:
+        f.write(text)
+    os.replace(path + ".tmp", path)
 
 
 if __name__ == "__main__":

@@ -127,5 +127,101 @@ GPX_HD float plog32(float a, int z = 0) {
     return tiny ? 0.0f : (fin ? v : m);
 }
 
+// The same four functions applied to N values at once, written stage by
+// stage across the values (every Horner step issues N independent FMAs), so
+// that the dependent binary64 chains of different values overlap.  Results
+// are identical to the one-value functions.
+template <int N>
+GPX_HD void sincos_n(float (&a)[N], bool want_cos, int z) {
+    double x[N], r[N], s[N], ps[N], pc[N];
+    int q[N];
+    bool big[N];
+    const double* S = kSin + z;
+    const double* C = kCos + z;
+    for (int j = 0; j < N; j++) {
+        x[j] = (double)a[j];
+        big[j] = !(fabs(x[j]) < 0x1p19);
+        const double xs = big[j] ? 0.0 : x[j];
+        const double kd = rint(xs * 0x1.45f306dc9c883p-1);
+        double t = fma(-kd, 0x1.921fb54442d18p+0, xs);
+        t = fma(-kd, 0x1.1a62633145c07p-54, t);
+        r[j] = fma(-kd, -0x1.f1976b7ed8fbcp-110, t);
+        s[j] = r[j] * r[j];
+        q[j] = (int)kd + (want_cos ? 1 : 0);
+        ps[j] = S[7];
+        pc[j] = C[7];
+    }
+    for (int k = 6; k >= 0; k--)
+        for (int j = 0; j < N; j++) {
+            ps[j] = fma(ps[j], s[j], S[k]);
+            pc[j] = fma(pc[j], s[j], C[k]);
+        }
+    for (int j = 0; j < N; j++) {
+        const double sn = fma(r[j] * s[j], ps[j], r[j]);
+        const double cs = fma(s[j], pc[j], 1.0);
+        const double v0 = (q[j] & 1) ? cs : sn;
+        double v = (q[j] & 2) ? -v0 : v0;
+        v = (x[j] == 0.0) ? (want_cos ? 1.0 : x[j]) : v;
+        if (big[j]) v = want_cos ? cos(x[j]) : sin(x[j]);
+        a[j] = (float)v;
+    }
+}
+
+template <int N>
+GPX_HD void expc_n(float (&a)[N], int z) {
+    double r[N], p[N];
+    int k[N];
+    float t[N];
+    bool ok[N];
+    const double* E = kExp + z;
+    for (int j = 0; j < N; j++) {
+        t[j] = (a[j] > 88.0f) ? 88.0f : a[j];
+        ok[j] = t[j] >= -104.0f;
+        const double x = ok[j] ? (double)t[j] : 0.0;
+        const double kd = rint(x * 0x1.71547652b82fep+0);
+        const double u = fma(-kd, 0x1.62e42fefa39efp-1, x);
+        r[j] = fma(-kd, 0x1.abc9e3b39803fp-56, u);
+        k[j] = (int)kd;
+        p[j] = E[11];
+    }
+    for (int i = 10; i >= 0; i--)
+        for (int j = 0; j < N; j++) p[j] = fma(p[j], r[j], E[i]);
+    for (int j = 0; j < N; j++) {
+        const double e = fma(r[j], fma(r[j], p[j], 1.0), 1.0);
+        const float v = (float)ldexp(e, k[j]);
+        a[j] = ok[j] ? v : (t[j] != t[j] ? t[j] : 0.0f);
+    }
+}
+
+template <int N>
+GPX_HD void plog_n(float (&a)[N], int z) {
+    double sv[N], t[N], p[N], ed[N];
+    float m[N];
+    bool tiny[N], fin[N];
+    const double* A = kAtanh + z;
+    for (int j = 0; j < N; j++) {
+        m[j] = fabsf(a[j]);
+        tiny[j] = m[j] < 1e-6f;
+        fin[j] = m[j] <= 0x1.fffffep+127f;
+        const double x = (fin[j] && !tiny[j]) ? (double)m[j] : 1.0;
+        int e;
+        const double f0 = frexp(x, &e);
+        const bool lo = f0 < 0x1.6a09e667f3bcdp-1;
+        const double f = lo ? f0 * 2.0 : f0;
+        ed[j] = (double)(lo ? e - 1 : e);
+        sv[j] = (f - 1.0) / (f + 1.0);
+        t[j] = sv[j] * sv[j];
+        p[j] = A[9];
+    }
+    for (int i = 8; i >= 0; i--)
+        for (int j = 0; j < N; j++) p[j] = fma(p[j], t[j], A[i]);
+    for (int j = 0; j < N; j++) {
+        const double s2 = sv[j] + sv[j];
+        const double lf = fma(s2 * t[j], p[j], s2);
+        const float v = (float)fma(ed[j], 0x1.62e42fefa3900p-1, fma(ed[j], 0x1.de6af278ece60p-46, lf));
+        a[j] = tiny[j] ? 0.0f : (fin[j] ? v : m[j]);
+    }
+}
+
 }  // namespace gmath
 }  // namespace gpx

@@ -170,7 +170,7 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
         for (int32_t i = 0; i < st.n_instr; i++) {
             const uint32_t op = pd.code[2 * (w + i)] & 15u;
             cost += op_cost(op);
-            pd.n_exit += (op >= GP_PDIV && op <= GP_PLOG);
+            pd.n_transc += (op >= GP_SIN && op <= GP_PLOG);
         }
         if (w > 0xFFFFFFFFll - 2 * (int64_t)st.n_instr)
             return fail(GP_E_INVAL, "programs exceed 2^32 device words");
@@ -235,7 +235,7 @@ gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cs
             const uint32_t wd = src[i];
             const int op = wd & 0xFF;
             cost += op_cost(op);
-            pd.n_exit += (op >= GP_PDIV);
+            pd.n_transc += (op >= GP_SIN);
             const int na = op < GP_SIN ? 2 : 1;
             for (int q = 0; q < na; q++) {
                 const int id = (int)((wd >> (16 + 8 * q)) & 0xFF);
@@ -409,7 +409,7 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
         return fail(GP_E_INVAL, "programs read feature %d; at most %d features are supported", pd.n_load - 1, GP_MAX_FEAT);
     const int vi = opt && opt->variant >= 0
                        ? opt->variant
-                       : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_exit / pd.n_instr : 0.0);
+                       : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth)
@@ -568,7 +568,7 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->n_instr = ps->pd.n_instr;
     info->n_gpop = ps->pd.n_gpop;
     info->variant = pick_core_variant(ps->pd.n_load, ps->pd.max_depth,
-                                      ps->pd.n_instr ? (double)ps->pd.n_exit / ps->pd.n_instr : 0.0);
+                                      ps->pd.n_instr ? (double)ps->pd.n_transc / ps->pd.n_instr : 0.0);
     info->pad = 0;
     return GP_OK;
 }

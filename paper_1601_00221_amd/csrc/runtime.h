@@ -51,7 +51,7 @@ struct ProgData {
     int32_t max_depth = 0;
     int64_t n_instr = 0;
     int64_t n_gpop = 0;     // GP operations per case: tree nodes or linear instructions
-    int64_t n_exit = 0;     // instructions that leave the core (protected division, sin/cos/exp/log)
+    int64_t n_transc = 0;   // sin/cos/exp/log instructions (evaluated in binary64 by compiled code)
     std::vector<uint32_t> code;
     std::vector<DevProg> progs;
     std::vector<uint32_t> cost;

@@ -4,6 +4,20 @@
 
 #include "gp_math.h"
 
+extern "C" void gm_eval_n8(int op, const float* in, float* out, int64_t n) {
+    for (int64_t i = 0; i + 8 <= n; i += 8) {
+        float a[8];
+        for (int j = 0; j < 8; j++) a[j] = in[i + j];
+        switch (op) {
+            case 4: gpx::gmath::sincos_n<8>(a, false, 0); break;
+            case 5: gpx::gmath::sincos_n<8>(a, true, 0); break;
+            case 6: gpx::gmath::expc_n<8>(a, 0); break;
+            default: gpx::gmath::plog_n<8>(a, 0); break;
+        }
+        for (int j = 0; j < 8; j++) out[i + j] = a[j];
+    }
+}
+
 extern "C" void gm_eval(int op, const float* in, float* out, int64_t n) {
     for (int64_t i = 0; i < n; i++) {
         const float a = in[i];

@@ -26,11 +26,17 @@ def gm(tmp_path_factory):
     subprocess.run(cmd, check=True)
     lib = C.CDLL(out)
     lib.gm_eval.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int64]
+    lib.gm_eval_n8.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int64]
 
-    def run(op, x):
+    def run(op, x, batched=False):
         x = np.ascontiguousarray(x, np.float32)
         y = np.empty_like(x)
-        lib.gm_eval(op, x.ctypes.data, y.ctypes.data, len(x))
+        if batched:
+            n = len(x) // 8 * 8
+            lib.gm_eval_n8(op, x.ctypes.data, y.ctypes.data, n)
+            lib.gm_eval(op, x[n:].ctypes.data, y[n:].ctypes.data, len(x) - n)
+        else:
+            lib.gm_eval(op, x.ctypes.data, y.ctypes.data, len(x))
         return y
     return run
 
@@ -70,3 +76,11 @@ def test_transcendental_matches_oracle(gm, op):
     # special arguments exactly
     sp = x[-28:]
     assert (d[-28:] == 0).all(), (synth.NAMES[op], sp[d[-28:] != 0])
+
+
+@pytest.mark.parametrize("op", [synth.SIN, synth.COS, synth.EXPC, synth.PLOG])
+def test_batched_form_is_identical(gm, op):
+    x = _args()
+    a = gm(op, x)
+    b = gm(op, x, batched=True)
+    assert ((a.view(np.int32) == b.view(np.int32)) | (np.isnan(a) & np.isnan(b))).all()
