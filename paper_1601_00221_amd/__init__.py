@@ -436,8 +436,9 @@ def out_tensor(kind, n_prog, n_cases, device="cuda"):
 
 
 # Sources that decide the evaluation kernel's machine code and launch shape.
-KERNEL_SOURCES = ("csrc/gen_core.py", "csrc/core_kernels.hip", "csrc/core_kernels.h", "csrc/core_host.cpp",
-                  "csrc/core_host.h", "csrc/runtime.cpp", "build.py")
+KERNEL_SOURCES = ("csrc/gen_core.py", "csrc/core_body.h", "csrc/gp_math.h", "csrc/core_kernels.hip",
+                  "csrc/core_kernels.h", "csrc/gp_internal.h", "csrc/core_host.cpp", "csrc/core_host.h",
+                  "csrc/runtime.cpp", "build.py")
 
 
 def kernel_source_digest() -> str:
