@@ -194,11 +194,14 @@ gp_status gp_eval_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
 gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, int32_t n_jobs, int32_t reps,
                         gp_batch_config* best, double* best_ms, void* stream);
 /* Compiled kernel variants: tile width t (case slots per lane), stack levels,
- * feature slots and the VGPRs left to compiled code (the interpreter core
- * owns the VGPRs from that number up).  The variant's kernel is named
- * k_core_<t>_<depth>_<n_feat>_<vgprs>.  Any pointer may be NULL. */
+ * feature slots, the VGPRs left to compiled code (the interpreter core owns
+ * the VGPRs from that number up) and flags: GP_VARIANT_NO_TRANSC marks a
+ * kernel without sin/cos/exp/log code, used for programs without them.  The
+ * variant's kernel is named k_core_<t>_<depth>_<n_feat>_<vgprs>, with "_a"
+ * appended for GP_VARIANT_NO_TRANSC.  Any pointer may be NULL. */
+enum { GP_VARIANT_NO_TRANSC = 1 };
 int32_t gp_num_variants(void);
-gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs);
+gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs, int32_t* flags);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: concurrent GP runs submit population evaluations against        */

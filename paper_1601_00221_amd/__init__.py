@@ -67,7 +67,7 @@ def lib():
             "gp_timing_read": [P, P, C.c_int],
             "gp_eval_batch": [P, i32, P, i32, P, P],
             "gp_tune_batch": [P, i32, P, i32, i32, P, P, P],
-            "gp_variant_info": [i32, P, P, P, P],
+            "gp_variant_info": [i32, P, P, P, P, P],
             "gp_serve_create": [P, P],
             "gp_serve_add_dataset": [P, P, i32, i64, P, P],
             "gp_serve_submit": [P, P, P],
@@ -332,10 +332,11 @@ def variants():
     L = lib()
     out = []
     for i in range(L.gp_num_variants()):
-        t, d, f, v = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f), C.byref(v)))
-        out.append({"t": t.value, "depth": d.value, "n_feat": f.value, "vgprs": v.value,
-                    "kernel": "k_core_%d_%d_%d_%d" % (t.value, d.value, f.value, v.value)})
+        t, d, f, v, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f), C.byref(v), C.byref(fl)))
+        arith = bool(fl.value & 1)
+        out.append({"t": t.value, "depth": d.value, "n_feat": f.value, "vgprs": v.value, "no_transc": arith,
+                    "kernel": "k_core_%d_%d_%d_%d%s" % (t.value, d.value, f.value, v.value, "_a" if arith else "")})
     return out
 
 

@@ -61,7 +61,7 @@ def _check_reserved(stderr: str, variant) -> None:
     compiler's inline-asm warnings: every VGPR the core clobbers must be
     reported as reserved."""
     gen_core = _gen_core()
-    t, d, nf, ncv = variant
+    t, d, nf, ncv = variant[:4]
     reserved = set()
     for m in re.finditer(r"clobber list contains reserved registers: ([^\[\n]*)", stderr):
         reserved.update(x.strip() for x in m.group(1).split(","))

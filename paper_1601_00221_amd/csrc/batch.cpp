@@ -47,9 +47,11 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
                      const gp_batch_config& cfg, BatchPlan& plan) {
     plan = BatchPlan();
     int n_load = 1, depth = 0;
+    bool any_transc = false;
     for (const BatchJobRef& j : jobs) {
         n_load = std::max(n_load, j.pd->n_load);
         depth = std::max(depth, j.pd->max_depth);
+        any_transc = any_transc || j.pd->n_transc > 0;
     }
     const int vi = cfg.variant;
     if (vi < 0 || vi >= core_variants()) return fail(GP_E_INVAL, "kernel variant %d does not exist", vi);
@@ -57,6 +59,8 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
     if (core_variant_nf(vi) < n_load || core_variant_d(vi) < depth)
         return fail(GP_E_INVAL, "variant %d (%d features, depth %d) cannot hold %d features / depth %d", vi,
                     core_variant_nf(vi), core_variant_d(vi), n_load, depth);
+    if (core_variant_arith(vi) && any_transc)
+        return fail(GP_E_INVAL, "variant %d has no sin/cos/exp/log code", vi);
     plan.vi = vi;
     const int32_t unit_prog = std::max(1, cfg.unit_programs);
     int64_t n_prog = 0;
@@ -324,9 +328,11 @@ static gp_status time_config(const std::vector<BatchJobRef>& jobs, const std::ve
 gp_status tune_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_dataset>& ds, int reps,
                      BatchScratch& sc, hipStream_t s, gp_batch_config* best, double* best_ms) {
     int n_load = 1, depth = 0;
+    bool any_transc = false;
     for (const BatchJobRef& j : jobs) {
         n_load = std::max(n_load, j.pd->n_load);
         depth = std::max(depth, j.pd->max_depth);
+        any_transc = any_transc || j.pd->n_transc > 0;
     }
     double best_t = 1e300;
     gp_batch_config b;
@@ -335,6 +341,7 @@ gp_status tune_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
     const int unit_sizes[] = {8, 32, 128};
     for (int vi = 0; vi < core_variants(); vi++) {
         if (core_variant_nf(vi) < n_load || core_variant_d(vi) < depth) continue;
+        if (core_variant_arith(vi) && any_transc) continue;
         for (int us : unit_sizes) {
             for (int pers = 1; pers >= 0; pers--) {
                 gp_batch_config c;
@@ -379,7 +386,9 @@ gp_batch_config default_config(const std::vector<BatchJobRef>& jobs) {
     }
     gp_batch_config c;
     memset(&c, 0, sizeof c);
-    c.variant = pick_core_variant(n_load, depth, transc_fraction(jobs));
+    bool any_transc = false;
+    for (const BatchJobRef& j : jobs) any_transc = any_transc || j.pd->n_transc > 0;
+    c.variant = pick_core_variant(n_load, depth, transc_fraction(jobs), any_transc);
     c.unit_programs = 32;
     c.persistent = 1;
     return c;
@@ -501,13 +510,15 @@ gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
 
 int32_t gp_num_variants(void) { return core_variants(); }
 
-gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs) {
+gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs,
+                          int32_t* flags) {
     clear_error();
     if (i < 0 || i >= core_variants()) return fail(GP_E_INVAL, "variant %d does not exist", i);
     if (t) *t = core_variant_t(i);
     if (depth) *depth = core_variant_d(i);
     if (n_feat) *n_feat = core_variant_nf(i);
     if (vgprs) *vgprs = core_variant_ncv(i);
+    if (flags) *flags = core_variant_arith(i) ? GP_VARIANT_NO_TRANSC : 0;
     return GP_OK;
 }
 

@@ -38,7 +38,7 @@ __device__ __forceinline__ float pdiv(float a, float b) { return (fabsf(b) < 1e-
 // Exit payload: byte 0 offset of A, byte 1 offset of B, byte 2 offset of the
 // destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
 // the constant, bit 5: B is the constant).
-template <int T, int V0>
+template <int T, int V0, bool AR>
 __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
     const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
     const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
@@ -68,6 +68,10 @@ __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
         for (int j = 0; j < T; j++) A[j] = c;
     } else {
         core_gather<T, V0>(oa, A);
+    }
+    if constexpr (AR) {
+        // arithmetic-only kernel: the host never runs sin/cos/exp/log programs on it
+        return;
     }
     // z is 0, but the compiler cannot know it: the coefficient tables are then
     // read with scalar loads, once per exit, instead of living in SGPRs
@@ -99,7 +103,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One work unit: a case tile and the programs order[q0 .. q1).  The kernel
 // has exactly one call site of the core (its labels are unique); in probe
 // mode the core only reports where its handler table starts.
-template <int T, int D, int NF, int V0>
+template <int T, int D, int NF, int V0, bool AR>
 __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, const float* y, int64_t N,
                                              int32_t n_load, int32_t kind, uint64_t pbase, uint32_t tile,
                                              uint32_t q0, uint32_t q1) {
@@ -128,18 +132,30 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
         }
         // first entry: burst the program's code into the scalar cache
         uint32_t pf_end = (a.probe || !a.prefetch) ? 0u : off + __builtin_amdgcn_readfirstlane(P.len) * 16u;
-        for (;;) {
+        // The core's asm (with its handler table and labels) must exist once in
+        // the kernel (the assembler rejects a second copy): the probe flag and
+        // the prefetch bound are laundered on every pass, so the loop is
+        // neither split on them nor peeled, and the call stays out of the loop
+        // header, so loop rotation does not copy it.
+        bool more = true;
+        while (more) {
             uint32_t pay, cst;
             uint64_t table;
-            Core<T, D, NF, V0>::run(code, off, pay, cst, a.probe, pf_end, table);
+            uint32_t probe = a.probe;
+            asm volatile("" : "+s"(probe));
+            Core<T, D, NF, V0>::run(code, off, pay, cst, probe, pf_end, table);
+            // later passes skip the prefetch; an opaque 0, so the first pass is not peeled off
             pf_end = 0u;
-            if (a.probe) {
+            asm volatile("" : "+s"(pf_end));
+            if (probe) {
                 if (threadIdx.x == 0) a.probe_out[0] = table;
                 return;
             }
-            if (((pay >> 24) & 15u) == CORE_OP_END) break;
-            do_exit<T, V0>(pay, cst);
-            off += 16u;
+            more = ((pay >> 24) & 15u) != CORE_OP_END;
+            if (more) {
+                do_exit<T, V0, AR>(pay, cst);
+                off += 16u;
+            }
         }
         float o[T];
         core_gather<T, V0>(0u, o);
@@ -188,13 +204,12 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
 
 // Units come either from a table (batched launches: persistent waves pull
 // them longest first from a counter, or one wave per unit) or implicitly
-// over one dataset: block unit b = (program group b div chunks, chunk b mod
-// chunks), and wave w of the block runs the group on tiles
-// (chunk * tiles_per_wave + i) * 4 + w, i = 0 .. tiles_per_wave - 1.  The
-// four waves of a block walk the same instruction stream side by side and
-// each walks it again for its next tile, so a group small enough for the
-// scalar cache is fetched from L2 once per block rather than once per tile.
-template <int T, int D, int NF, int V0>
+// over one dataset: block unit b = (group quad b div chunks, chunk b mod
+// chunks); wave w of the block runs program group 4 * quad + w on tiles
+// chunk * tiles_per_wave + i, i = 0 .. tiles_per_wave - 1.  The four waves of
+// a block work on the same tiles with different instruction streams, so
+// their scalar-cache misses do not fall on the same cycles.
+template <int T, int D, int NF, int V0, bool AR>
 __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -209,8 +224,9 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
         u = (b & 7u) * (nb >> 3) + (b >> 3);
         if (!a.probe) {
             if (u >= (uint32_t)a.n_units) return;
-            grp = u / (uint32_t)a.chunks;
+            grp = (u / (uint32_t)a.chunks) * 4u + wib;
             chunk = u % (uint32_t)a.chunks;
+            if (grp >= (uint32_t)a.n_groups) return;
         }
     }
     for (uint32_t it = 0;; ++it) {
@@ -223,7 +239,7 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
             if (u != 0 || wib != 0) return;
         } else if (!table) {
             if (it >= (uint32_t)a.tiles_per_wave) return;
-            tile = (chunk * (uint32_t)a.tiles_per_wave + it) * 4u + wib;
+            tile = chunk * (uint32_t)a.tiles_per_wave + it;
             if (tile >= (uint32_t)a.tiles) return;
             q0 = a.group_off[grp];
             q1 = a.group_off[grp + 1];
@@ -254,7 +270,7 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
             kind = jd.kind;
             pbase = jd.part_base;
         }
-        process_unit<T, D, NF, V0>(a, X, y, N, n_load, kind, pbase, __builtin_amdgcn_readfirstlane(tile),
+        process_unit<T, D, NF, V0, AR>(a, X, y, N, n_load, kind, pbase, __builtin_amdgcn_readfirstlane(tile),
                                __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1));
         if (a.probe) return;
     }
@@ -262,11 +278,12 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
 
 // One kernel per variant.  amdgpu_num_vgpr(n) lets the compiler allocate 2n
 // VGPRs on gfx950 (checked at build time against the compiler's
-// reserved-register report); the core owns v[V0 ...].
-#define GPX_KERNEL(T, D, NF, V0)                                                                        \
+// reserved-register report); the core owns v[V0 ...].  AR: no sin/cos/exp/log
+// code (for programs without them).
+#define GPX_KERNEL(T, D, NF, V0, AR, NAME)                                                              \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr((V0) / 2))) void                   \
-        k_core_##T##_##D##_##NF##_##V0(CoreArgs a) {                                                    \
-        k_core_body<T, D, NF, V0>(a);                                                                   \
+        k_core_##NAME(CoreArgs a) {                                                                     \
+        k_core_body<T, D, NF, V0, (AR) != 0>(a);                                                        \
     }
 
 }  // namespace gpx

@@ -41,11 +41,11 @@ const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
 int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
 int core_reg_levels(int vi) { return kCoreVariants[vi].d > GPX_LIN_REGS ? kCoreVariants[vi].d : GPX_LIN_REGS; }
 
-int pick_core_variant(int n_load, int depth, double transc_frac) {
+int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc) {
     // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
     // outside the core) run best with room for that code (no spills) and as
     // many waves per SIMD as that leaves, to hide its latency; the others with
-    // the widest tile.  Ties go to the fewest feature slots, then the fewest
+    // the widest tile, on a kernel without that code if they use none of it.  Ties go to the fewest feature slots, then the fewest
     // handlers (least code).  (Measured on the 4096 x 65,536 tree workloads.)
     const bool heavy = transc_frac > 0.2;
     int best = -1;
@@ -56,11 +56,11 @@ int pick_core_variant(int n_load, int depth, double transc_frac) {
     };
     auto score = [&](const CoreVariantDesc& v) {
         if (heavy) return (v.ncv >= 64) * 100000000 + waves(v) * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
-        return (v.ncv <= 64) * 100000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
+        return v.arith * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
     };
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
-        if (v.nf < n_load || v.d < depth) continue;
+        if (v.nf < n_load || v.d < depth || (v.arith && has_transc)) continue;
         if (best < 0 || score(v) > score(kCoreVariants[best])) best = i;
     }
     return best;
@@ -321,5 +321,6 @@ int core_variant_t(int vi) { return kCoreVariants[vi].t; }
 int core_variant_ncv(int vi) { return kCoreVariants[vi].ncv; }
 int core_variant_d(int vi) { return kCoreVariants[vi].d; }
 int core_variant_nf(int vi) { return kCoreVariants[vi].nf; }
+int core_variant_arith(int vi) { return kCoreVariants[vi].arith; }
 
 }  // namespace gpx

@@ -52,8 +52,8 @@ struct CoreArgs {
     const JobDesc* jobs;
     const DatasetDesc* datasets;
     uint32_t* counter;          // next unit, persistent form
-    // implicit units: block unit b = (group b div chunks, chunk b mod chunks);
-    // a chunk is 4 * tiles_per_wave consecutive tiles
+    // implicit units: block unit b = (group quad b div chunks, chunk b mod
+    // chunks); a chunk is tiles_per_wave consecutive tiles
     const uint32_t* group_off;
     const float* X;
     const float* y;
@@ -66,7 +66,7 @@ struct CoreArgs {
     int32_t tiles_per_wave;
     int32_t chunks;
     int32_t prefetch;           // burst-load each program's code into the scalar cache first
-    int32_t pad1;
+    int32_t n_groups;           // program groups (implicit units)
     uint32_t probe;             // nonzero: write the handler table address and return
     double* partials;
     float* cases_out;

@@ -43,25 +43,35 @@ import sys
 SLOT = 64                 # bytes per handler slot; longer handlers take several
 LIN_REGS = 8              # register slots reserved for linear programs (and stack levels)
 
-# (T, D, NF, NCV) variants: T case slots per lane, D stack levels, NF feature
-# slots, NCV VGPRs left to the compiler (the core owns v[NCV ...]).  Work
-# that leaves the core (sin/cos/exp/log in binary64, protected division)
-# runs in the compiler's VGPRs: programs rich in it take a variant with a
-# large NCV (fewer waves per SIMD), arithmetic programs one with NCV = 40.
+# (T, D, NF, NCV, AR) variants: T case slots per lane, D stack levels, NF
+# feature slots, NCV VGPRs left to the compiler (the core owns v[NCV ...]),
+# AR = 1 for a kernel without the sin/cos/exp/log code (for programs that use
+# none; its compiled part is small, so nothing spills).  Work that leaves the
+# core (sin/cos/exp/log in binary64, protected division) runs in the
+# compiler's VGPRs: programs rich in it take a variant with room for it.
 VARIANTS = [
-    (8, 6, 8, 40),
-    (8, 6, 8, 128),
-    (8, 8, 8, 40),
-    (4, 8, 8, 40),
-    (4, 8, 16, 40),
-    (4, 12, 32, 40),
-    (8, 8, 8, 128),
-    (4, 8, 16, 128),
-    (4, 12, 32, 80),
-    (4, 8, 8, 64),
-    (4, 8, 8, 96),
-    (4, 8, 16, 64),
+    (8, 6, 8, 40, 0),
+    (8, 6, 8, 128, 0),
+    (8, 8, 8, 40, 0),
+    (4, 8, 8, 40, 0),
+    (4, 8, 16, 40, 0),
+    (4, 12, 32, 40, 0),
+    (8, 8, 8, 128, 0),
+    (4, 8, 16, 128, 0),
+    (4, 12, 32, 80, 0),
+    (4, 8, 8, 64, 0),
+    (4, 8, 8, 96, 0),
+    (4, 8, 16, 64, 0),
+    (8, 6, 8, 40, 1),
+    (8, 8, 8, 40, 1),
+    (4, 8, 16, 40, 1),
+    (4, 12, 32, 40, 1),
 ]
+
+
+def vname(v):
+    """Kernel name suffix of a variant: T_D_NF_NCV, plus _a when it has no sin/cos/exp/log code."""
+    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], "_a" if v[4] else "")
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
 OP_ID = {"add": 0, "sub": 1, "mul": 2}
@@ -380,7 +390,7 @@ def main(out_dir):
     lines.append("enum CoreKind {" + ", ".join("CK_%s = %d" % (k, i) for i, k in enumerate(KINDS)) + "};")
     lines.append("")
     lines.append("#define GPX_CORE_VARIANTS(X) \\")
-    lines.append(" \\\n".join("    X(%d, %d, %d, %d)" % v for v in VARIANTS))
+    lines.append(" \\\n".join("    X(%d, %d, %d, %d, %d)" % v for v in VARIANTS))
     lines.append("")
     clob_s = ", ".join('"s%d"' % n for n in (63, 64, 65, 66, 67, 70, 71, 72, 76, 77))
     lines.append("template <int T, int D, int NF, int V0> struct Core;")
@@ -389,8 +399,13 @@ def main(out_dir):
     for T, V0 in sorted(set((v[0], v[3]) for v in VARIANTS)):
         lines.append(gather_scatter(T, V0))
     host = []
-    for (T, D, NF, NCV) in VARIANTS:
+    seen = {}
+    for (T, D, NF, NCV, AR) in VARIANTS:
+        if (T, D, NF, NCV) in seen:       # same core as another variant
+            host.append((T, D, NF, NCV, AR) + seen[(T, D, NF, NCV)])
+            continue
         tag, V0, FO, hs, nslots = gen_variant(T, D, NF, NCV)
+        seen[(T, D, NF, NCV)] = (tag, hs, nslots)
         text = asm_text(T, D, NF, tag, hs)
         clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
         assert NCV + FO + NF * T <= 256
@@ -409,20 +424,26 @@ def main(out_dir):
         lines.append("#endif")
         lines.append("    }")
         lines.append("};")
-        host.append((T, D, NF, NCV, tag, hs, nslots))
+        host.append((T, D, NF, NCV, AR, tag, hs, nslots))
     lines.append("")
     lines.append("struct CoreHandlerKey { uint8_t kind, op; int8_t p1, p2; };")
-    for (T, D, NF, NCV, tag, hs, nslots) in host:
+    done = set()
+    for (T, D, NF, NCV, AR, tag, hs, nslots) in host:
+        if tag in done:
+            continue
+        done.add(tag)
         lines.append("static const CoreHandlerKey kCoreKeys_%s[] = {" % tag)
         lines.append("    " + ", ".join("{%d,%d,%d,%d}" % (h.kind, h.op, h.p1, h.p2) for h in hs))
         lines.append("};")
         lines.append("static const uint16_t kCoreSlots_%s[] = {" % tag)
         lines.append("    " + ", ".join(str(h.slot) for h in hs))
         lines.append("};")
-    lines.append("struct CoreVariantDesc { int t, d, nf, ncv; const CoreHandlerKey* keys; const uint16_t* slots; int n; int table_bytes; };")
+    lines.append("struct CoreVariantDesc { int t, d, nf, ncv, arith; const CoreHandlerKey* keys; const uint16_t* slots; "
+                 "int n; int table_bytes; };")
     lines.append("static const CoreVariantDesc kCoreVariants[] = {")
-    for (T, D, NF, NCV, tag, hs, nslots) in host:
-        lines.append("    {%d, %d, %d, %d, kCoreKeys_%s, kCoreSlots_%s, %d, %d}," % (T, D, NF, NCV, tag, tag, len(hs), nslots * SLOT))
+    for (T, D, NF, NCV, AR, tag, hs, nslots) in host:
+        lines.append("    {%d, %d, %d, %d, %d, kCoreKeys_%s, kCoreSlots_%s, %d, %d}," % (T, D, NF, NCV, AR, tag, tag, len(hs),
+                                                                                    nslots * SLOT))
     lines.append("};")
     path = os.path.join(out_dir, "core_gen.inc")
     write_if_changed(path, "\n".join(lines) + "\n")
@@ -430,13 +451,13 @@ def main(out_dir):
     disp = ["// Generated by gen_core.py -- do not edit.", "#pragma once", "",
             "typedef hipError_t (*CoreLaunchFn)(const CoreArgs&, uint32_t, hipStream_t);",
             "typedef int (*CoreOccupancyFn)();"]
-    for (T, D, NF, NCV, tag, hs, nslots) in host:
-        name = "%d_%d_%d_%d" % (T, D, NF, NCV)
+    for (T, D, NF, NCV, AR, tag, hs, nslots) in host:
+        name = vname((T, D, NF, NCV, AR))
         disp.append("hipError_t core_launch_%s(const CoreArgs& a, uint32_t blocks, hipStream_t s);" % name)
         disp.append("int core_occupancy_%s();" % name)
         tu = ["// Generated by gen_core.py -- do not edit.  Kernel variant %s." % tag,
               '#include "core_body.h"', "", "namespace gpx {",
-              "GPX_KERNEL(%d, %d, %d, %d)" % (T, D, NF, NCV), "",
+              "GPX_KERNEL(%d, %d, %d, %d, %d, %s)" % (T, D, NF, NCV, AR, name), "",
               "hipError_t core_launch_%s(const CoreArgs& a, uint32_t blocks, hipStream_t s) {" % name,
               "    hipLaunchKernelGGL(k_core_%s, dim3(blocks), dim3(256), 0, s, a);" % name,
               "    return hipGetLastError();", "}", "",
@@ -445,19 +466,19 @@ def main(out_dir):
               "    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_core_%s, 256, 0) != hipSuccess) n = 1;" % name,
               "    return n;", "}", "}  // namespace gpx", ""]
         write_if_changed(os.path.join(out_dir, "core_v_%s.hip" % name), "\n".join(tu))
-    names = ["%d_%d_%d_%d" % (T, D, NF, NCV) for (T, D, NF, NCV, tag, hs, nslots) in host]
+    names = [vname(h[:5]) for h in host]
     disp.append("static const CoreLaunchFn kCoreLaunch[] = {%s};" % ", ".join("core_launch_" + n for n in names))
     disp.append("static const CoreOccupancyFn kCoreOccupancy[] = {%s};"
                 % ", ".join("core_occupancy_" + n for n in names))
     write_if_changed(os.path.join(out_dir, "core_dispatch.inc"), "\n".join(disp) + "\n")
-    for (T, D, NF, NCV, tag, hs, nslots) in host:
-        print("%s: %d handlers, %d slots (%d KiB)" % (tag, len(hs), nslots, nslots * SLOT // 1024))
+    for (T, D, NF, NCV, AR, tag, hs, nslots) in host:
+        print("%s%s: %d handlers, %d slots (%d KiB)" % (tag, "a" if AR else "", len(hs), nslots, nslots * SLOT // 1024))
     return path
 
 
 def variant_sources():
     """File names of the generated per-variant translation units."""
-    return ["core_v_%d_%d_%d_%d.hip" % v for v in VARIANTS]
+    return ["core_v_%s.hip" % vname(v) for v in VARIANTS]
 
 
 def write_if_changed(path, text):

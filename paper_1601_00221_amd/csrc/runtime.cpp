@@ -318,11 +318,12 @@ static gp_status groups_for(const ProgData& pd, DevProgs& dp, int32_t G, hipStre
 }
 
 // Launch shape of one evaluation.  Programs are dealt into G groups of
-// about `group_instr` core instructions (small enough that a block's group
-// stays in the scalar cache while its waves walk it tile after tile); each
-// block runs one group on a chunk of 4 * tiles_per_wave tiles.  The chunk is
-// as long as still leaves `target_blocks` blocks; with few tiles, groups are
-// made smaller instead, down to one program, so the chip still fills.
+// about `group_instr` core instructions; each block runs four groups (one
+// per wave) on a chunk of tiles_per_wave tiles.  Chunks lengthen only while
+// four times `target_blocks` blocks remain; with few tiles, groups are made
+// smaller instead, down to one program, so the chip still fills.  (Group
+// size and chunk length were chosen by sweeps on the 4096-program tree and
+// linear workloads.)
 struct LaunchShape {
     int32_t G, tiles_per_wave, chunks;
 };
@@ -334,29 +335,27 @@ static int32_t env_int(const char* name, int32_t dflt) {
     return x > 0 && x < (1L << 30) ? (int32_t)x : dflt;
 }
 
-// Burst-load each program's code into the scalar cache before running it
-// (GP2D_CODE_PREFETCH=0 turns it off, for measurement).
 int32_t code_prefetch() {
     const char* v = getenv("GP2D_CODE_PREFETCH");
     return (v && v[0] == '0') ? 0 : 1;
 }
 
 static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOptions* opt) {
-    const int32_t group_instr = opt && opt->group_instr > 0 ? opt->group_instr : env_int("GP2D_GROUP_INSTR", 4096);
+    const int32_t group_instr = opt && opt->group_instr > 0 ? opt->group_instr : env_int("GP2D_GROUP_INSTR", 2048);
     const int32_t target_blocks = opt && opt->target_blocks > 0 ? opt->target_blocks : env_int("GP2D_TARGET_BLOCKS", 4096);
-    const int64_t quads = (tiles + 3) / 4;
     int64_t G = (pd.n_instr + group_instr - 1) / group_instr;
-    if (G * quads < target_blocks) G = (target_blocks + quads - 1) / quads;
+    if (((G + 3) / 4) * tiles < target_blocks) G = 4 * ((target_blocks + tiles - 1) / tiles);
     G = std::max<int64_t>(1, std::min<int64_t>(G, pd.n_prog));
+    const int64_t quads = (G + 3) / 4;
     int32_t tpw = opt && opt->tiles_per_wave > 0 ? opt->tiles_per_wave : env_int("GP2D_TILES_PER_WAVE", 0);
     if (tpw <= 0) {
         tpw = 1;
-        while (tpw < 16 && G * ((quads + 2 * tpw - 1) / (2 * tpw)) >= target_blocks) tpw *= 2;
+        while (tpw < 16 && quads * ((tiles + 2 * tpw - 1) / (2 * tpw)) >= 4 * (int64_t)target_blocks) tpw *= 2;
     }
     LaunchShape L;
     L.G = (int32_t)G;
     L.tiles_per_wave = tpw;
-    L.chunks = (int32_t)((quads + tpw - 1) / tpw);
+    L.chunks = (int32_t)((tiles + tpw - 1) / tpw);
     return L;
 }
 
@@ -409,10 +408,12 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
         return fail(GP_E_INVAL, "programs read feature %d; at most %d features are supported", pd.n_load - 1, GP_MAX_FEAT);
     const int vi = opt && opt->variant >= 0
                        ? opt->variant
-                       : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0);
+                       : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0,
+                                           pd.n_transc > 0);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
-    if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth)
+    if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth ||
+        (core_variant_arith(vi) && pd.n_transc > 0))
         return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
     gp_status st;
     if ((st = core_ready(vi, s)) != GP_OK) return st;
@@ -425,7 +426,7 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     const int32_t tiles = (int32_t)tiles64;
     const LaunchShape L = launch_shape(pd, tiles, opt);
     const int32_t G = L.G;
-    const int64_t units = (int64_t)L.chunks * G;
+    const int64_t units = (int64_t)L.chunks * ((G + 3) / 4);
     if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
     const uint32_t *order, *goff;
     if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
@@ -449,6 +450,7 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     a.tiles_per_wave = L.tiles_per_wave;
     a.chunks = L.chunks;
     a.prefetch = code_prefetch();
+    a.n_groups = G;
     a.partials = (double*)w.partials.p;
     a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
     uint32_t blocks = (uint32_t)units;
@@ -568,7 +570,8 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->n_instr = ps->pd.n_instr;
     info->n_gpop = ps->pd.n_gpop;
     info->variant = pick_core_variant(ps->pd.n_load, ps->pd.max_depth,
-                                      ps->pd.n_instr ? (double)ps->pd.n_transc / ps->pd.n_instr : 0.0);
+                                      ps->pd.n_instr ? (double)ps->pd.n_transc / ps->pd.n_instr : 0.0,
+                                      ps->pd.n_transc > 0);
     info->pad = 0;
     return GP_OK;
 }

@@ -313,7 +313,8 @@ gp_status gp_serve_submit(gp_server* sv, const gp_job* req, uint64_t* ticket) {
     r->need = request_bytes(r->pd, ds[req->dataset].n_cases);
     r->gpop = r->pd.n_gpop * ds[req->dataset].n_cases;
     r->variant = pick_core_variant(r->pd.n_load, r->pd.max_depth,
-                                   r->pd.n_instr ? (double)r->pd.n_transc / (double)r->pd.n_instr : 0.0);
+                                   r->pd.n_instr ? (double)r->pd.n_transc / (double)r->pd.n_instr : 0.0,
+                                   r->pd.n_transc > 0);
     if (r->variant < 0 && r->pd.n_prog > 0) {
         std::lock_guard<std::mutex> g(S.mu);
         S.n_rejected++;

@@ -38,7 +38,7 @@ def f32(x):
 
 class CoreEmu:
     def __init__(self, variant_index):
-        T, D, NF, NCV = gen_core.VARIANTS[variant_index]
+        T, D, NF, NCV = gen_core.VARIANTS[variant_index][:4]
         tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF, NCV)
         self.T, self.D, self.NF, self.V0, self.FO = T, D, NF, V0, FO
         self.by_slot = {h.slot: h for h in hs}
@@ -202,7 +202,7 @@ def _same(a, b):
 
 @pytest.mark.parametrize("vi", range(len(gen_core.VARIANTS)))
 def test_core_trees_match_oracle(vi):
-    T, D, NF, NCV = gen_core.VARIANTS[vi]
+    T, D, NF, NCV = gen_core.VARIANTS[vi][:4]
     F = min(NF, 9)
     rng = synth.rng_for(300 + vi)
     pop = synth.ptc2_population(rng, 30, synth.FULL, F, 1, 90, 0.25)
@@ -225,7 +225,7 @@ def test_core_trees_match_oracle(vi):
 
 @pytest.mark.parametrize("vi", range(len(gen_core.VARIANTS)))
 def test_core_linear_match_oracle(vi):
-    T, D, NF, NCV = gen_core.VARIANTS[vi]
+    T, D, NF, NCV = gen_core.VARIANTS[vi][:4]
     F = min(NF, 12)
     rng = synth.rng_for(400 + vi)
     pop = synth.linear_population(rng, 25, 1, 60, synth.FULL, 8, F, n_const=3)
@@ -240,7 +240,7 @@ def test_core_linear_match_oracle(vi):
 
 
 def test_every_handler_is_reachable_and_in_its_slot():
-    for vi, (T, D, NF, NCV) in enumerate(gen_core.VARIANTS):
+    for vi, (T, D, NF, NCV, _) in enumerate(gen_core.VARIANTS):
         tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF, NCV)
         slots = [h.slot for h in hs]
         assert slots == sorted(slots) and len(set(slots)) == len(slots)

@@ -54,9 +54,13 @@ def test_batch_matches_individual_evaluation_bit_for_bit():
     jobs = [gp.make_job(pop, ds, kind, o) for (pop, ds, kind), o in zip(spec, outs)]
     configs = [None]
     for vi, v in enumerate(gp.variants()):
-        if v["depth"] >= 12:
+        if v["depth"] >= 12 and not v["no_transc"]:
             for up, pers in ((8, 1), (128, 0), (32, 1)):
                 configs.append(gp.BatchConfig(vi, up, pers, 0))
+        elif v["depth"] >= 12:
+            # a kernel without sin/cos/exp/log code refuses these programs
+            with pytest.raises(gp.GPError):
+                gp.gp_eval_batch(dd, jobs, gp.BatchConfig(vi, 8, 1, 0))
     ref = [_alone(pop, data[ds][0], data[ds][1], kind) for pop, ds, kind in spec]
     for cfg in configs:
         say("batch config", None if cfg is None else cfg.as_dict())
@@ -191,3 +195,29 @@ def test_served_under_tight_memory_budget():
     for o, r in zip(outs, ref):
         assert np.array_equal(o.cpu().numpy(), r)
     assert st["completed"] == 12
+
+
+def test_every_variant_on_arithmetic_programs():
+    """Every kernel variant, including those without sin/cos/exp/log code,
+    gives the oracle's fitness (within the fitness tolerance) on programs
+    over {+,-,*,/p}."""
+    import torch
+    rng = synth.rng_for(41)
+    F = 8
+    N = 512 * 5 + 77
+    X = synth.uniform_cases(rng, F, N, -3, 3)
+    y = synth.gaussian_noise(rng, N, 1.0)
+    trees = synth.ptc2_population(rng, 60, synth.BASIC, F, 1, 60, 1 / 9)
+    lin = synth.linear_population(rng, 60, 1, 60, synth.BASIC, 8, F, n_const=2)
+    dd = [(dev(X), dev(y))]
+    ref_t = oracle.eval_tree(trees.tok, trees.cst, trees.off, X, y, "mse")
+    ref_l = oracle.eval_linear(lin.code, lin.off, lin.cst, lin.cst_off, lin.n_reg, X, y, "mse")
+    for vi, v in enumerate(gp.variants()):
+        say("variant", v["kernel"])
+        out_t = gp.out_tensor("mse", trees.n_prog, 0)
+        out_l = gp.out_tensor("mse", lin.n_prog, 0)
+        jobs = [gp.make_job(trees, 0, "mse", out_t), gp.make_job(lin, 0, "mse", out_l)]
+        gp.gp_eval_batch(dd, jobs, gp.BatchConfig(vi, 8, 1, 0))
+        torch.cuda.synchronize()
+        assert fitness_close(out_t.cpu().numpy(), ref_t).all()
+        assert fitness_close(out_l.cpu().numpy(), ref_l).all()
