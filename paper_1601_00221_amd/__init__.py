@@ -437,7 +437,7 @@ def out_tensor(kind, n_prog, n_cases, device="cuda"):
 
 
 # Sources that decide the evaluation kernel's machine code and launch shape.
-KERNEL_SOURCES = ("csrc/gen_core.py", "csrc/core_body.h", "csrc/gp_math.h", "csrc/core_kernels.hip",
+KERNEL_SOURCES = ("csrc/gen_core.py", "csrc/core_body.h", "csrc/gp_math.h", "csrc/gp_math_tables.h", "csrc/core_kernels.hip",
                   "csrc/core_kernels.h", "csrc/gp_internal.h", "csrc/core_host.cpp", "csrc/core_host.h",
                   "csrc/runtime.cpp", "build.py")
 

@@ -39,7 +39,7 @@ __device__ __forceinline__ float pdiv(float a, float b) { return (fabsf(b) < 1e-
 // destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
 // the constant, bit 5: B is the constant).
 template <int T, int V0, bool AR>
-__device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
+__device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits, const double* tab) {
     const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
     const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
     const float c = __uint_as_float(cbits);
@@ -77,19 +77,12 @@ __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits) {
     // read with scalar loads, once per exit, instead of living in SGPRs
     int z = 0;
     asm volatile("" : "+s"(z));
-    // sin and cos take the T slots stage by stage, side by side; exp and log
-    // one slot after another (each measured the faster way)
+    // the T slots of each function side by side; the reduction tables are in LDS
     switch (op) {
-        case GP_SIN: gmath::sincos_n<T>(A, false, z); break;
-        case GP_COS: gmath::sincos_n<T>(A, true, z); break;
-        case GP_EXPC:
-#pragma unroll
-            for (int j = 0; j < T; j++) A[j] = gmath::expc32(A[j], z);
-            break;
-        default:  // GP_PLOG
-#pragma unroll
-            for (int j = 0; j < T; j++) A[j] = gmath::plog32(A[j], z);
-            break;
+        case GP_SIN: gmath::sincos_n<T>(A, false, tab, z); break;
+        case GP_COS: gmath::sincos_n<T>(A, true, tab, z); break;
+        case GP_EXPC: gmath::expc_n<T>(A, tab, z); break;
+        default: gmath::plog_n<T>(A, tab, z); break;  // GP_PLOG
     }
     core_scatter<T, V0>(od, A);
 }
@@ -106,7 +99,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int T, int D, int NF, int V0, bool AR>
 __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, const float* y, int64_t N,
                                              int32_t n_load, int32_t kind, uint64_t pbase, uint32_t tile,
-                                             uint32_t q0, uint32_t q1) {
+                                             uint32_t q0, uint32_t q1, const double* tab) {
     static_assert(T % 4 == 0, "a tile holds whole 256-case blocks");
     constexpr int RB = D > GPX_LIN_REGS ? D : GPX_LIN_REGS;   // register/stack levels before the features
     const uint32_t lane = threadIdx.x & 63u;
@@ -153,7 +146,7 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             }
             more = ((pay >> 24) & 15u) != CORE_OP_END;
             if (more) {
-                do_exit<T, V0, AR>(pay, cst);
+                do_exit<T, V0, AR>(pay, cst, tab);
                 off += 16u;
             }
         }
@@ -211,6 +204,14 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
 // their scalar-cache misses do not fall on the same cycles.
 template <int T, int D, int NF, int V0, bool AR>
 __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
+    // the transcendentals' reduction tables, copied into LDS by the whole block
+    const double* tab = nullptr;
+    if constexpr (!AR) {
+        __shared__ double s_tab[gmath::kTabSize];
+        gmath::tab_fill(s_tab, (int)threadIdx.x, (int)blockDim.x);
+        __syncthreads();
+        tab = s_tab;
+    }
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool table = a.units != nullptr;
@@ -271,7 +272,7 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
             pbase = jd.part_base;
         }
         process_unit<T, D, NF, V0, AR>(a, X, y, N, n_load, kind, pbase, __builtin_amdgcn_readfirstlane(tile),
-                               __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1));
+                               __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1), tab);
         if (a.probe) return;
     }
 }

@@ -84,3 +84,32 @@ def test_batched_form_is_identical(gm, op):
     a = gm(op, x)
     b = gm(op, x, batched=True)
     assert ((a.view(np.int32) == b.view(np.int32)) | (np.isnan(a) & np.isnan(b))).all()
+
+
+def test_tables_regenerate_from_their_definitions(tmp_path):
+    """The committed reduction tables are what the generator computes from
+    the mathematical definitions (300-bit mpmath)."""
+    import importlib.util
+    gen = os.path.join(ROOT, "paper_1601_00221_amd", "csrc", "gen_math_tables.py")
+    spec = importlib.util.spec_from_file_location("gen_math_tables", gen)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    out = mod.main(str(tmp_path))
+    with open(out) as f, open(os.path.join(ROOT, "paper_1601_00221_amd", "csrc", "gp_math_tables.h")) as g:
+        assert f.read() == g.read()
+
+
+def test_table_spot_values():
+    """A few entries against closed forms: sin(pi/4) = cos(pi/4) = 2^-1/2,
+    2^(32/64) = 2^1/2, and 128/128 = 1 with log 1 = 0."""
+    import re
+    text = open(os.path.join(ROOT, "paper_1601_00221_amd", "csrc", "gp_math_tables.h")).read()
+
+    def arr(name):
+        body = re.search(name + r"\[\d+\] = \{([^}]*)\}", text).group(1)
+        return [float.fromhex(x.strip()) for x in body.split(",") if x.strip()]
+    h = float.fromhex("0x1.6a09e667f3bcdp-1")    # nearest binary64 to 2^-1/2
+    assert arr("kSinJ")[8] == h and arr("kCosJ")[8] == h
+    assert arr("kExp2J")[32] == float.fromhex("0x1.6a09e667f3bcdp+0")
+    j0 = int(re.search(r"GPX_LOG_J0 (\d+)", text).group(1))
+    assert arr("kLogInv")[128 - j0] == 1.0 and arr("kLogHi")[128 - j0] == 0.0
