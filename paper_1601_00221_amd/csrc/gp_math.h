@@ -39,12 +39,13 @@
 #include <stdint.h>
 #include <string.h>
 
+// Tables are constexpr arrays (not device variables), so device code reaches
+// them PC-relative instead of through the global offset table.
+#define GPX_TABLE constexpr
 #if defined(__HIPCC__)
 #define GPX_HD __host__ __device__ __forceinline__
-#define GPX_TABLE __constant__
 #else
 #define GPX_HD static inline
-#define GPX_TABLE static
 #endif
 
 namespace gpx {
@@ -66,7 +67,7 @@ enum : int {
 // Series coefficients, one block: sin (r^3 .. r^9), cos (r^2 .. r^8),
 // exp (r^2 .. r^6), log1p (r^2 .. r^8).
 enum : int { kCoSin = 0, kCoCos = 4, kCoExp = 8, kCoLog = 13, kCoSize = 20 };
-GPX_TABLE const double kCoef[kCoSize] = {
+GPX_TABLE double kCoef[kCoSize] = {
     // (-1)^k / (2k+1)!, k = 1 .. 4
     -0x1.5555555555555p-3, 0x1.1111111111111p-7, -0x1.a01a01a01a01ap-13, 0x1.71de3a556c734p-19,
     // (-1)^k / (2k)!, k = 1 .. 4
