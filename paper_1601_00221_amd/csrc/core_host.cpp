@@ -100,14 +100,21 @@ gp_status core_ready(int vi, hipStream_t s) {
 
 namespace {
 
+// Handlers come in two phases (records are fetched two at a time, see
+// gen_core.py): instructions alternate A, B, A, ... and every entry into the
+// core -- a program's start, the return from an exit -- begins with A.
+constexpr int kPhaseB = 0x80;
+
 struct Emitter {
     const VariantMap& m;
     std::vector<uint32_t>& out;
     char* err;
     bool ok = true;
+    int phase = 0;
 
     void put(int kind, int op, int p1, int p2, uint32_t pay, uint32_t cst) {
-        auto it = m.slot.find(key_of(kind, op, p1, p2));
+        auto it = m.slot.find(key_of(kind | phase, op, p1, p2));
+        phase ^= kPhaseB;
         if (it == m.slot.end()) {
             snprintf(err, 256, "no core handler for kind %d op %d (%d, %d)", kind, op, p1, p2);
             ok = false;
@@ -126,6 +133,7 @@ struct Emitter {
             (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16) |
                 ((op | (fl << 4)) << 24),
             cst);
+        phase = 0;   // the core is entered again after an exit
     }
 };
 
@@ -297,6 +305,9 @@ static gp_status translate_with(const ProgData& pd, int vi, const VariantMap& m,
         progs[p].code_off = (uint32_t)start;   // words
         progs[p].len = (uint32_t)((code.size() - start) / 4);
     }
+    // the core reads records two at a time, up to one record past a program's
+    // last one: pad the end of the code
+    code.insert(code.end(), 16, 0u);
     return GP_OK;
 }
 

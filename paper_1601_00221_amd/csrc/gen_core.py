@@ -302,12 +302,83 @@ def gen_variant(T, D, NF, NCV):
         epilogue(h)
         hs.append(h)
 
+    # ---------------------------------------------------------------- phases
+    hs = [phase_a(h, tag) for h in hs] + [phase_b(h, tag) for h in hs]
+
     # ---------------------------------------------------------------- layout
     slot = 0
     for h in hs:
         h.slot = slot
         slot += (h.size + SLOT - 1) // SLOT
     return tag, V0, FO, hs, slot
+
+
+# Two copies of every handler.  Records are fetched two at a time: a phase-B
+# handler (its own record in s[68:71]) loads the next two records into
+# s[64:71] with one s_load_dwordx8, works, waits, and jumps to the next
+# instruction's phase-A handler; a phase-A handler (its record in s[64:67],
+# the next one already in s[68:71]) works and jumps on without loading or
+# waiting.  So only every second instruction waits for the scalar cache.
+# The host gives instructions alternating phases, A first after every entry
+# into the core (program start, return from an exit), which loads the first
+# two records itself.  The handlers are written once (as for a single record
+# in s[64:67], constant copied to s72, indexes in s66/s70/s71); these
+# functions rewrite them for each phase.
+PHASE_B = 0x80
+
+
+def _copy(h, kind):
+    c = Handler(kind, h.op, h.p1, h.p2)
+    return c
+
+
+def phase_a(h, tag):
+    c = _copy(h, h.kind)
+    if h.kind == K["EXIT"]:
+        for x in h.lines:
+            c.emit(x, 4)
+        return c
+    body = []
+    for x in h.lines:
+        if x == "s_mov_b32 s72, s67" or x == "s_mov_b32 s70, s66" or x.startswith("s_add_u32 s62") \
+                or x.startswith("s_load_dwordx4") or x.startswith("s_waitcnt") or x.startswith("s_setpc"):
+            continue
+        x = x.replace("s_lshr_b32 s71, s66, 8", "s_lshr_b32 s74, s66, 8")
+        x = x.replace("s_set_gpr_idx_on s70,", "s_set_gpr_idx_on s66,").replace("s_set_gpr_idx_on s71,", "s_set_gpr_idx_on s74,")
+        x = x.replace("s72", "s67")
+        body.append(x)
+    for x in body:
+        c.emit(x, 8 if x.startswith("s_load") else 4)
+    c.emit("s_add_u32 s62, s62, 16", 4)
+    c.emit("s_setpc_b64 s[68:69]", 4)
+    return c
+
+
+def phase_b(h, tag):
+    c = _copy(h, h.kind | PHASE_B)
+    if h.kind == K["EXIT"]:
+        c.emit("s_set_gpr_idx_off", 4)
+        c.emit("s_mov_b32 s66, s70", 4)
+        c.emit("s_mov_b32 s67, s71", 4)
+        c.emit("s_branch .Lgpx_end_%s" % tag, 4)
+        return c
+    for x in h.lines:
+        if x == "s_mov_b32 s72, s67":
+            x = "s_mov_b32 s72, s71"
+        elif x == "s_mov_b32 s70, s66":
+            x = "s_mov_b32 s73, s70"
+        elif x == "s_lshr_b32 s71, s66, 8":
+            x = "s_lshr_b32 s74, s70, 8"
+        elif x.startswith("s_load_dwordx4"):
+            x = "s_load_dwordx8 s[64:71], s[60:61], s62"
+        elif x.startswith("s_set_gpr_idx_on s66,"):
+            x = x.replace("s_set_gpr_idx_on s66,", "s_set_gpr_idx_on s70,")
+        elif x.startswith("s_set_gpr_idx_on s70,"):
+            x = x.replace("s_set_gpr_idx_on s70,", "s_set_gpr_idx_on s73,")
+        elif x.startswith("s_set_gpr_idx_on s71,"):
+            x = x.replace("s_set_gpr_idx_on s71,", "s_set_gpr_idx_on s74,")
+        c.emit(x, 8 if x.startswith("s_load") else 4)
+    return c
 
 
 def asm_text(T, D, NF, tag, hs):
@@ -321,15 +392,16 @@ def asm_text(T, D, NF, tag, hs):
     L.append("s_branch .Lgpx_end_%s" % tag)
     L.append(".Lgpx_run_%s:" % tag)
     # Burst-load the program's remaining 64-byte lines (from the current
-    # record's line up to byte offset s68) into the scalar cache, up to 8
-    # loads in flight, so the handlers' one-record-ahead loads then hit.
-    # s68 = 0 skips it (re-entry after an exit).  s69 only receives data.
+    # record's line up to byte offset s75) into the scalar cache, up to 8
+    # loads in flight, so the handlers' record loads then hit.  s75 = 0 skips
+    # it (re-entry after an exit).  s76 only receives data; every load is
+    # waited for before the first handler runs.
     L.append("s_and_b32 s73, s62, 0xffffffc0")
     L.append("s_mov_b32 s74, 0")
     L.append(".Lgpx_pf_%s:" % tag)
-    L.append("s_cmp_lt_u32 s73, s68")
+    L.append("s_cmp_lt_u32 s73, s75")
     L.append("s_cbranch_scc0 .Lgpx_pfdone_%s" % tag)
-    L.append("s_load_dword s69, s[60:61], s73")
+    L.append("s_load_dword s76, s[60:61], s73")
     L.append("s_add_u32 s73, s73, 64")
     L.append("s_add_u32 s74, s74, 1")
     L.append("s_cmp_lt_u32 s74, 8")
@@ -338,7 +410,7 @@ def asm_text(T, D, NF, tag, hs):
     L.append("s_mov_b32 s74, 0")
     L.append("s_branch .Lgpx_pf_%s" % tag)
     L.append(".Lgpx_pfdone_%s:" % tag)
-    L.append("s_load_dwordx4 s[64:67], s[60:61], s62")
+    L.append("s_load_dwordx8 s[64:71], s[60:61], s62")   # this record and the next: phase A
     L.append("s_waitcnt lgkmcnt(0)")
     L.append("s_setpc_b64 s[64:65]")
     L.append(".p2align %d" % (SLOT.bit_length() - 1))
@@ -418,9 +490,9 @@ def main(out_dir):
         lines.append("#ifdef __HIP_DEVICE_COMPILE__")
         lines.append('        asm volatile("%s"' % text)
         lines.append('            : "+{s62}"(off), "={s66}"(pay), "={s67}"(cst), "={s[76:77]}"(table)')
-        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe), "{s68}"(pf_end)')
-        lines.append('            : %s, "s64", "s65", "s69", "s70", "s71", "s72", "s73", "s74", "scc", "m0", "memory");'
-                     % clob_v)
+        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe), "{s75}"(pf_end)')
+        lines.append('            : %s, "s64", "s65", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "scc", "m0",'
+                     ' "memory");' % clob_v)
         lines.append("#endif")
         lines.append("    }")
         lines.append("};")

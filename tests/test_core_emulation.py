@@ -65,12 +65,12 @@ class CoreEmu:
             return (op, int(r[1:]), set(modes.split(",")))
         if op in ("s_set_gpr_idx_off", "s_waitcnt", "s_nop"):
             return (op,)
-        if op == "s_load_dwordx4":
-            assert rest == "s[64:67], s[60:61], s62", rest
+        if op == "s_load_dwordx8":
+            assert rest == "s[64:71], s[60:61], s62", rest
             return (op,)
         if op == "s_setpc_b64":
-            assert rest == "s[64:65]"
-            return (op,)
+            assert rest in ("s[64:65]", "s[68:69]"), rest
+            return (op, int(rest[2:4]))
         if op == "s_branch":
             assert ".Lgpx_end_" in rest
             return (op,)
@@ -83,11 +83,13 @@ class CoreEmu:
         (offset, payload, constant) as the asm block hands them back."""
         s = self.s
         s[62] = off
-        w = code[off // 4: off // 4 + 4]
-        s[64], s[65], s[66], s[67] = (int(x) for x in w)
+        # entry: this record and the next one, then the phase-A handler
+        for k in range(8):
+            s[64 + k] = int(code[off // 4 + k])
         idx_on, m0, modes = False, 0, set()
+        pair = 64
         while True:
-            addr = s[64] | (s[65] << 32)
+            addr = s[pair] | (s[pair + 1] << 32)
             rel = addr - BASE
             assert rel >= 0 and rel % gen_core.SLOT == 0, hex(addr)
             slot = rel // gen_core.SLOT
@@ -101,10 +103,12 @@ class CoreEmu:
                     idx_on = False
                 elif op in ("s_waitcnt", "s_nop"):
                     pass
-                elif op == "s_load_dwordx4":
+                elif op == "s_load_dwordx8":
                     o = s[62] // 4
-                    s[64], s[65], s[66], s[67] = (int(x) for x in code[o:o + 4])
+                    for k in range(8):
+                        s[64 + k] = int(code[o + k])
                 elif op == "s_setpc_b64":
+                    pair = ins[1]
                     break
                 elif op == "s_branch":
                     return s[62], s[66], s[67]
@@ -246,8 +250,17 @@ def test_every_handler_is_reachable_and_in_its_slot():
         assert slots == sorted(slots) and len(set(slots)) == len(slots)
         for h in hs:
             assert h.size <= gen_core.SLOT * ((h.size + gen_core.SLOT - 1) // gen_core.SLOT)
-            if h.kind != gen_core.K["EXIT"]:
-                assert h.lines[-1] == "s_setpc_b64 s[64:65]"
-                # the next instruction is loaded before any index-mode vector op reads s[64:67]
-                assert any(x.startswith("s_load_dwordx4") for x in h.lines)
+            if h.kind & 0x7F == gen_core.K["EXIT"]:
+                continue
+            if h.kind & gen_core.PHASE_B:
+                # loads the next two records, waits, jumps to the first of them
+                assert h.lines[-1] == "s_setpc_b64 s[64:65]" and h.lines[-2] == "s_waitcnt lgkmcnt(0)"
+                loads = [i for i, x in enumerate(h.lines) if x.startswith("s_load_dwordx8")]
+                assert len(loads) == 1
+                # everything read from its own record (s[68:71]) is read before the load
+                assert not any(re.search(r"\bs(68|69|70|71)\b", x) for x in h.lines[loads[0] + 1:])
+            else:
+                # works from s[64:67] and jumps to the record already in s[68:69]
+                assert h.lines[-1] == "s_setpc_b64 s[68:69]"
+                assert not any(x.startswith(("s_load", "s_waitcnt")) for x in h.lines)
         assert V0 + FO + NF * T <= 256
