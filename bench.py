@@ -22,6 +22,9 @@ Workloads (synthetic, seeded):
   served       32 concurrent GP runs in a closed loop submitting population
                evaluations to the continuous-batching server; p50/p99 latency
                and throughput, compared with one launch per request
+  compare-1d   kernel GPop/s of the 2D-stack evaluator against the
+               one-dimensional-stack (BlockGP) comparator in postfix and
+               stack-operand form, on the scale-tree and arith-tree workloads
   copy-calibration
                a plain 256 MiB device copy, three times: the reference for
                scaling the FETCH_SIZE / WRITE_SIZE counters to bytes
@@ -409,6 +412,70 @@ def bench_served(args):
     return res
 
 
+# ----------------------------------------------------------------------------
+# 2D stack against the one-dimensional-stack (BlockGP) comparator
+# ----------------------------------------------------------------------------
+PAPER_2D_OVER_1D = {"rpn": 1.14, "lgp": 1.40}   # section 4.2 and 5: Tables 4 over 3, 8 over 7 (GTX 670)
+
+
+def bench_compare_1d(args):
+    """Kernel time of the 2D-stack evaluator and of the 1D comparator in its
+    postfix (RPN) and stack-operand (LGP) forms on the same population,
+    cases and targets; GPop/s from HIP events around each launch."""
+    import torch
+    import paper_1601_00221_amd as gp
+    out_all = {}
+    value = None
+    step_2d = None
+    for base in ("scale-tree", "arith-tree"):
+        w = make_workload(base)
+        N, P = w.X.shape[1], w.pop.n_prog
+        Xd = torch.from_numpy(w.X).cuda()
+        yd = gpu_targets(w.target, Xd, w.noise)
+        ps = gp.ProgSet.tree(w.pop.tok, w.pop.cst, w.pop.off, w.X.shape[0])
+        gpop = ps.info()["n_gpop"] * N
+        out = gp.out_tensor(w.kind, P, N)
+        runs = {"2d": lambda: ps.eval(Xd, yd, w.kind, out)}
+        for form in ("rpn", "lgp"):
+            runs["1d_" + form] = (lambda f: lambda: gp.gp_eval_tree_1d(w.pop.tok, w.pop.cst, w.pop.off, Xd, yd,
+                                                                      w.kind, out, form=f))(form)
+        res = {}
+        fits = {}
+        for name, fn in runs.items():
+            steps = args.steps if name == "2d" else max(1, min(args.steps, 5))
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            gp.timing_read(reset=True)
+            gp.timing_enable(True)
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            gp.timing_enable(False)
+            n_launch, ms = gp.timing_read(reset=True)
+            kern_s = ms / 1e3 / max(n_launch, 1)
+            res[name] = {"gpops": gpop / kern_s, "kernel_ms": kern_s * 1e3, "launches": n_launch}
+            fits[name] = out.cpu().numpy().copy()
+            log("%s %s: %.3f ms, %.4f T GPop/s" % (base, name, kern_s * 1e3, gpop / kern_s / 1e12))
+        for form in ("rpn", "lgp"):
+            res["2d_over_1d_" + form] = res["2d"]["gpops"] / res["1d_" + form]["gpops"]
+            f1, f2 = fits["1d_" + form], fits["2d"]
+            res["max_rel_fitness_diff_" + form] = float(np.nanmax(np.abs(f1 - f2) / np.maximum(np.abs(f2), 1e-30)))
+        res.update({"n_prog": P, "n_cases": N, "gpop_per_step": gpop})
+        out_all[w.name] = res
+        if value is None:
+            value, step_2d = res["2d"]["gpops"], res["2d"]["kernel_ms"] / 1e3
+            kernel = kernel_name(ps.info()["variant"])
+            roof = roofline(gpop, step_2d, kernel, w.name)
+        ps.close()
+    config = {"workload": "compare-1d", "bases": list(out_all)}
+    r = base_result(args, value, step_2d, config)
+    r["roofline"] = roof
+    r["compare_1d"] = out_all
+    r["paper_2d_over_1d"] = PAPER_2D_OVER_1D
+    return r
+
+
 def copy_calibration():
     """A plain device copy of known size for scaling the HBM counters."""
     import torch
@@ -442,6 +509,8 @@ def main():
         res = bench_batched(args)
     elif args.workload == "served":
         res = bench_served(args)
+    elif args.workload == "compare-1d":
+        res = bench_compare_1d(args)
     else:
         res = bench_single(args)
     print(json.dumps(res), flush=True)

@@ -110,6 +110,28 @@ gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* 
                          const float* X, int32_t n_feat, int64_t n_cases, const float* y,
                          int32_t kind, void* out, void* stream);
 
+/* One-dimensional-stack comparator (the BlockGP design the paper measures
+ * its 2D stack against: section 4.2, Tables 3 and 7).  One workgroup of 256
+ * threads per program with the program copied into LDS; thread t evaluates
+ * cases t, t + 256, ... one at a time with a stack of its own in private
+ * (scratch) memory.  Same program, case, fitness and arithmetic conventions
+ * as gp_eval_tree, and the same fitness values up to the order of the
+ * binary64 summation.  form selects the interpreted code:
+ *   GP_1D_RPN  the tree in postfix order (one instruction per node; operands
+ *              popped from the stack, as in the paper's RPN interpreter);
+ *   GP_1D_LGP  the tree lowered to the stack-operand linear form that
+ *              gp_eval_tree also uses (section 5, Table 7).
+ * Limits: at most GP_1D_MAX_LEN instructions per program (the program must
+ * fit in LDS) and GP_1D_MAX_STACK stack values; GP_E_DEPTH beyond them.
+ * kind GP_OUT_CASES writes the per-case outputs.  Meant for measurement;
+ * gp_eval_tree is the evaluator. */
+enum { GP_1D_RPN = 0, GP_1D_LGP = 1 };
+#define GP_1D_MAX_LEN 4096
+#define GP_1D_MAX_STACK 64
+gp_status gp_eval_tree_1d(const int32_t* tok, const float* cst, const int64_t* off, int32_t n_prog,
+                          const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                          int32_t kind, int32_t form, void* out, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Resident program sets: lower and upload once, evaluate many times        */
 /* (a GP generation evaluated on several datasets, or timed repeatedly).    */

@@ -56,6 +56,7 @@ def lib():
         P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
             "gp_eval_tree": [P, P, P, i32, P, i32, i64, P, i32, P, P],
+            "gp_eval_tree_1d": [P, P, P, i32, P, i32, i64, P, i32, i32, P, P],
             "gp_eval_linear": [P, P, P, P, i32, i32, P, i32, i64, P, i32, P, P],
             "gp_progset_tree": [P, P, P, i32, i32, P, P],
             "gp_progset_linear": [P, P, P, P, i32, i32, i32, P, P],
@@ -145,6 +146,21 @@ def gp_eval_tree(tok, cst, off, X, y, kind, out, n_feat=None, stream=None):
     F, N = int(X.shape[0]), int(X.shape[1])
     check(lib().gp_eval_tree(tp, cp, op, len(off) - 1, dptr(X), n_feat or F, N, dptr(y),
                              kind_id(kind), dptr(out), stream_ptr(stream)))
+
+
+GP_1D_FORMS = {"rpn": 0, "lgp": 1}
+
+
+def gp_eval_tree_1d(tok, cst, off, X, y, kind, out, form="rpn", n_feat=None, stream=None):
+    """The one-dimensional-stack comparator: same arguments as gp_eval_tree,
+    plus form "rpn" (postfix code) or "lgp" (the stack-operand linear form)."""
+    tok, tp = _np(tok, np.int32)
+    cst, cp = _np(cst, np.float32)
+    off, op = _np(off, np.int64)
+    F, N = int(X.shape[0]), int(X.shape[1])
+    fid = GP_1D_FORMS[form] if isinstance(form, str) else int(form)
+    check(lib().gp_eval_tree_1d(tp, cp, op, len(off) - 1, dptr(X), n_feat or F, N, dptr(y),
+                                kind_id(kind), fid, dptr(out), stream_ptr(stream)))
 
 
 def gp_eval_linear(code, off, cst, cst_off, n_reg, X, y, kind, out, n_feat=None, stream=None):

@@ -79,6 +79,7 @@ struct Workspace {
     DevBuf partials;
     Staging staging;
     std::map<int, DevProgs> oneshot;   // by core variant
+    DevBuf bg_code, bg_meta;           // programs of the one-dimensional-stack comparator
 };
 
 struct EvalOptions {

@@ -1,0 +1,121 @@
+"""GPU parity of the one-dimensional-stack comparator (gp_eval_tree_1d, the
+BlockGP design of section 4.2 in postfix form and in the stack-operand
+linear form of section 5) against the CPU oracle, element by element.
+
+The order in which subtrees are evaluated does not change any value, and
+sin/cos/exp/log are the same device functions as in the 2D-stack kernel, so
+per-case outputs must equal the 2D kernel's bit for bit, and the oracle's
+under the same bar as the 2D kernel (bit-exact without transcendentals).
+Fitness sums differ from the 2D kernel only in the binary64 summation
+order."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1601_00221_amd as gp
+import synth
+from tests import progs
+from tests.gpu_util import (dev, fitness_close, gpu_tree, has_transcendental_tree, same_bits, say,
+                            well_conditioned_tree)
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ("rpn", "lgp")
+
+
+def same_rel(a, b, tol):
+    """Equal within tol relative, or the same non-finite value."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        close = np.abs(a - b) <= tol * np.abs(b)
+    return close | (a == b) | (np.isnan(a) & np.isnan(b))
+
+
+def gpu_tree_1d(pop, X, y, kind, form):
+    import torch
+    out = gp.out_tensor(kind, pop.n_prog, X.shape[1])
+    gp.gp_eval_tree_1d(pop.tok, pop.cst, pop.off, dev(X), dev(y) if y is not None else None, kind, out,
+                       form=form)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("n_feat,n_cases", [(8, 3001), (1, 777), (32, 600), (3, 65), (5, 1)])
+def test_1d_trees_match_oracle(form, n_feat, n_cases):
+    rng = synth.rng_for(300 + n_feat)
+    pop = synth.ptc2_population(rng, 120, synth.FULL, n_feat, 1, 200, 1.0 / (n_feat + 1))
+    X = synth.uniform_cases(rng, n_feat, n_cases, -5, 5)
+    y = synth.gaussian_noise(rng, n_cases, 1.0)
+    say("1d %s F=%d N=%d: cases" % (form, n_feat, n_cases))
+    got = gpu_tree_1d(pop, X, None, "cases", form)
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    tr = has_transcendental_tree(pop)
+    assert same_bits(got[~tr], ref[~tr]).all()
+    assert same_bits(got, ref).mean() >= 0.9999
+    say("1d %s: against the 2D kernel" % form)
+    assert same_bits(got, gpu_tree(pop, X, None, "cases")).all()
+    for kind in ("mse", "sum_abs"):
+        say("1d %s F=%d N=%d: %s" % (form, n_feat, n_cases, kind))
+        f = gpu_tree_1d(pop, X, y, kind, form)
+        ref_f, ok = well_conditioned_tree(pop, X, y, kind)
+        close = fitness_close(f, ref_f)
+        assert close[~tr].all()
+        assert not (~close & ok).any()
+        f2 = gpu_tree(pop, X, y, kind)
+        assert same_rel(f, f2, 1e-6).all()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_1d_hits_exact(form):
+    rng = synth.rng_for(311)
+    pop = synth.ptc2_population(rng, 100, synth.BASIC, 4, 1, 120, 0.2)
+    X = synth.uniform_cases(rng, 4, 2500, -3, 3)
+    _, y = synth.sign_labels(rng, X)
+    say("1d %s hits" % form)
+    got = gpu_tree_1d(pop, X, y, "hits", form)
+    ref = oracle.eval_tree(pop.tok, pop.cst, pop.off, X, y, "hits")
+    assert (got == ref).all()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_1d_degenerate_programs(form):
+    """Single terminals, a right-deep chain (postfix stack of 60 values), a
+    left-deep chain of 4095 nodes (the longest accepted), every function."""
+    right = "x0"
+    for k in range(59):
+        right = "(+ x%d %s)" % (k % 3, right)
+    exprs = ["x2", "0.25", "(sin x0)", "(cos 1.5)", "(exp x1)", "(log x2)", "(/ x0 0)", right,
+             "(* (- x0 x1) (+ x2 (/ x1 x0)))"]
+    # left-deep chain (op_2046 (... (op_0 x1 x0) ...) x2), built in prefix
+    # order directly (too deep for the s-expression parser)
+    ops = [(synth.ADD, synth.SUB, synth.MUL, synth.PDIV)[k % 4] for k in range(2047)]
+    tok = np.array(ops[::-1] + [synth.var_tok(1)] + [synth.var_tok(k % 3) for k in range(2047)], np.int32)
+    lists = [progs.parse(e) for e in exprs] + [(tok, np.zeros(len(tok), np.float32))]
+    pop = synth.trees_from_lists(lists)
+    assert pop.sizes().max() == 4095
+    rng = synth.rng_for(312)
+    X = synth.uniform_cases(rng, 3, 1000, -2, 2)
+    say("1d %s degenerate" % form)
+    got = gpu_tree_1d(pop, X, None, "cases", form)
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    tr = has_transcendental_tree(pop)
+    assert same_bits(got[~tr], ref[~tr]).all()
+    assert same_bits(got, gpu_tree(pop, X, None, "cases")).all()
+
+
+def test_1d_rejects_before_launch():
+    import torch
+    X = torch.zeros((1, 8), device="cuda")
+    out = torch.zeros(1, device="cuda")
+    deep = "x0"
+    for _ in range(64):
+        deep = "(+ x0 %s)" % deep
+    pop = progs.pop(deep)
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_eval_tree_1d(pop.tok, pop.cst, pop.off, X, None, "cases", out, form="rpn")
+    assert e.value.status == gp.GP_E_DEPTH
+    # the stack-operand form needs one level for the same tree
+    out2 = gp.out_tensor("cases", 1, 8)
+    gp.gp_eval_tree_1d(pop.tok, pop.cst, pop.off, X, None, "cases", out2, form="lgp")
+    torch.cuda.synchronize()
+    assert (out2.cpu().numpy() == 0).all()
