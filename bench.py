@@ -22,6 +22,9 @@ Workloads (synthetic, seeded):
   served       32 concurrent GP runs in a closed loop submitting population
                evaluations to the continuous-batching server; p50/p99 latency
                and throughput, compared with one launch per request
+  mux20        the 20-multiplexer: 4096 PTC2 trees of 1-256 nodes over
+               {AND,OR,NAND,NOR} and the 20 inputs, all 2^20 cases bit-packed
+               into 32,768 words per input, hit count (sub-machine-code GP)
   compare-1d   kernel GPop/s of the 2D-stack evaluator against the
                one-dimensional-stack (BlockGP) comparator in postfix and
                stack-operand form, on the scale-tree and arith-tree workloads
@@ -48,6 +51,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_T = 157.3   # MI355X vector FP32 peak, TFLOP/s (one GP operation counted as one FP32 operation)
+# 32-bit vector logic: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, 32 cases per lane-operation
+PEAK_BITOP_T = 256 * 4 * 16 * 2.4e9 * 32 / 1e12
 
 
 def log(*a):
@@ -476,6 +481,73 @@ def bench_compare_1d(args):
     return r
 
 
+# ----------------------------------------------------------------------------
+# Boolean trees over bit-packed cases (sub-machine-code GP, 20-multiplexer)
+# ----------------------------------------------------------------------------
+def bench_mux20(args):
+    import torch
+    import paper_1601_00221_amd as gp
+    import synth
+    w = synth.mux_workload()
+    P, n = w.pop.n_prog, w.n_cases
+    Xd = torch.from_numpy(w.Xw.view(np.int32)).cuda()
+    yd = torch.from_numpy(w.yw.view(np.int32)).cuda()
+    ps = gp.ProgSet.boolean(w.pop.tok, w.pop.off, w.Xw.shape[0])
+    info = ps.info()
+    gpop_per_step = info["n_gpop"] * n
+    out = torch.empty(P, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        ps.eval(Xd, yd, "hits", out, n_cases=n)
+    torch.cuda.synchronize()
+    gp.timing_read(reset=True)
+    gp.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ps.eval(Xd, yd, "hits", out, n_cases=n)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gp.timing_enable(False)
+    n_launch, kernel_ms = gp.timing_read(reset=True)
+    step_s = (t1 - t0) / args.steps
+    kern_s = kernel_ms / 1e3 / max(n_launch, 1)
+    value = gpop_per_step / step_s
+    log("step %.3f ms, kernel %.3f ms, %.1f T GPop/s" % (step_s * 1e3, kern_s * 1e3, value / 1e12))
+    config = {"workload": w.name, "n_prog": P, "n_cases": n, "n_feat": int(w.Xw.shape[0]), "fitness": "hits",
+              "gpop_per_step": gpop_per_step, "cases_per_word": 32}
+    res = base_result(args, value, step_s, config)
+    res["dtype"] = "u32"
+    res.pop("pct_vector_fp32_peak", None)
+    kernel = kernel_name(info["variant"])
+    achieved = gpop_per_step / kern_s / 1e12
+    traffic, src = traffic_record(w.name, kernel)
+    res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_BITOP_T, "unit": "T bit-op/s",
+                       "frac": achieved / PEAK_BITOP_T, "traffic": traffic, "kernel": kernel,
+                       "kernel_ms": kern_s * 1e3}
+    if traffic is not None:
+        res["roofline"]["traffic_source"] = src
+    res["paper_gpops"] = 1.411185e12   # the paper's best 20-multiplexer rate (GTX 670), for context
+    if not args.no_cpu:
+        import oracle
+        log("cpu baseline ...")
+        # programs in an evenly spread order until the time budget is spent
+        idx = np.argsort((np.arange(P) * 2654435761) % P, kind="stable")
+        t = time.perf_counter()
+        k = 0
+        ops = 0
+        while k < len(idx) and time.perf_counter() - t < args.cpu_budget:
+            sub = w.pop.subset(idx[k:k + 1])
+            oracle.eval_bool(sub.tok, sub.off, w.Xw, n, w.yw)
+            ops += int(np.sum(sub.sizes())) * n
+            k += 1
+        dt = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": ops / dt, "unit": "GPop/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d programs (spread over the population) x all %d cases, %.3g GPop in %.1f s"
+                                         % (k, n, ops, dt)}
+    ps.close()
+    return res
+
+
 def copy_calibration():
     """A plain device copy of known size for scaling the HBM counters."""
     import torch
@@ -511,6 +583,8 @@ def main():
         res = bench_served(args)
     elif args.workload == "compare-1d":
         res = bench_compare_1d(args)
+    elif args.workload == "mux20":
+        res = bench_mux20(args)
     else:
         res = bench_single(args)
     print(json.dumps(res), flush=True)

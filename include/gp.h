@@ -75,6 +75,8 @@ typedef enum {
 enum {
     GP_ADD = 0, GP_SUB = 1, GP_MUL = 2, GP_PDIV = 3,
     GP_SIN = 4, GP_COS = 5, GP_EXPC = 6, GP_PLOG = 7,
+    /* Boolean functions, for gp_eval_bool only (bitwise on 32 packed cases) */
+    GP_AND = 8, GP_OR = 9, GP_NAND = 10, GP_NOR = 11,
     GP_VAR = 64, GP_CONST = 65
 };
 
@@ -132,6 +134,27 @@ gp_status gp_eval_tree_1d(const int32_t* tok, const float* cst, const int64_t* o
                           const float* X, int32_t n_feat, int64_t n_cases, const float* y,
                           int32_t kind, int32_t form, void* out, void* stream);
 
+/* Sub-machine-code evaluation of Boolean trees (the paper's multiplexer
+ * problem: sections 3 and 4.2, Table 2 and the last row of Tables 3-10).
+ * Cases are bit-packed: bit b of word w is case 32 * w + b, and every
+ * function is applied to 32 cases at once with one bitwise operation, so
+ * one interpreted instruction covers 64 lanes x T words x 32 cases.
+ *   tok/off  HOST prefix trees in CSR form over GP_AND, GP_OR, GP_NAND,
+ *            GP_NOR (binary) and GP_VAR terminals; no constants.
+ *   X        DEVICE uint32, feature-major: word w of input f is
+ *            X[f * n_words + w], n_words = ceil(n_cases / 32).
+ *   y        DEVICE uint32[n_words], the target bits.
+ *   kind     GP_FIT_HITS: out is DEVICE int32[n_prog], the number of cases
+ *            whose output bit equals the target bit (bits past n_cases in
+ *            the last word are ignored); GP_OUT_CASES: out is DEVICE
+ *            uint32[n_prog * n_words], the output words (y may be NULL).
+ * n_cases is at most 2^31 - 1.  GP_E_INVAL for any other opcode or kind, GP_E_DEPTH for programs deeper
+ * than the Boolean kernels' stacks.  GP operations are counted per case:
+ * nodes x n_cases. */
+gp_status gp_eval_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, const uint32_t* X,
+                       int32_t n_feat, int64_t n_cases, const uint32_t* y, int32_t kind, void* out,
+                       void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Resident program sets: lower and upload once, evaluate many times        */
 /* (a GP generation evaluated on several datasets, or timed repeatedly).    */
@@ -157,6 +180,11 @@ gp_status gp_progset_tree(const int32_t* tok, const float* cst, const int64_t* o
 gp_status gp_progset_linear(const uint32_t* code, const int64_t* off, const float* cst,
                             const int64_t* cst_off, int32_t n_prog, int32_t n_reg, int32_t n_feat,
                             void* stream, gp_progset** ps);
+/* Boolean trees as in gp_eval_bool.  gp_progset_eval then takes X and y as
+ * DEVICE uint32 words (bit-packed cases, as in gp_eval_bool), n_cases counts
+ * cases (bits), and kind is GP_FIT_HITS or GP_OUT_CASES. */
+gp_status gp_progset_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, int32_t n_feat, void* stream,
+                          gp_progset** ps);
 /* Evaluate a resident set on a case matrix with n_feat >= the set's n_feat. */
 gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases,
                           const float* y, int32_t kind, void* out, void* stream);
@@ -218,10 +246,13 @@ gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
 /* Compiled kernel variants: tile width t (case slots per lane), stack levels,
  * feature slots, the VGPRs left to compiled code (the interpreter core owns
  * the VGPRs from that number up) and flags: GP_VARIANT_NO_TRANSC marks a
- * kernel without sin/cos/exp/log code, used for programs without them.  The
+ * kernel without sin/cos/exp/log code, used for programs without them;
+ * GP_VARIANT_BOOLEAN (with GP_VARIANT_NO_TRANSC) a kernel of the Boolean
+ * function set for gp_eval_bool, whose slots are 32-bit words.  The
  * variant's kernel is named k_core_<t>_<depth>_<n_feat>_<vgprs>, with "_a"
- * appended for GP_VARIANT_NO_TRANSC.  Any pointer may be NULL. */
-enum { GP_VARIANT_NO_TRANSC = 1 };
+ * appended for an arithmetic-only and "_b" for a Boolean kernel.  Any
+ * pointer may be NULL. */
+enum { GP_VARIANT_NO_TRANSC = 1, GP_VARIANT_BOOLEAN = 2 };
 int32_t gp_num_variants(void);
 gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs, int32_t* flags);
 
@@ -305,7 +336,8 @@ gp_status gp_lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t
                         uint32_t* words, int64_t max_words, gp_lower_stats* stats);
 
 /* Translate programs into the instruction stream of kernel variant
- * `variant`'s interpreter core, taking its handler table to start at
+ * `variant`'s interpreter core (trees of the Boolean function set for a
+ * GP_VARIANT_BOOLEAN variant, cst then unused), taking its handler table to start at
  * table_base (64-byte aligned; the library finds the real address on the
  * device itself).  Host only.  Each core instruction is 4 uint32 words:
  * handler address (2 words), operand offsets, constant.  words (may be

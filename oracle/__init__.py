@@ -58,6 +58,8 @@ def lib():
         L.orc_rpn_eval.argtypes = [P, P, C.c_int64, P, C.c_int64, C.c_int64, P, P, P]
         L.orc_rpn_to_lgp.argtypes = [P, P, C.c_int64, P, P]
         L.orc_lgp_eval.argtypes = [P, C.c_int64, P, C.c_int64, C.c_int64, P, P, P]
+        L.orc_bool_outputs.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_int64, P]
+        L.orc_bool_hits.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_int64, P, P]
         L.orc_apply.argtypes = [C.c_int, C.c_float, C.c_float]
         L.orc_apply.restype = C.c_float
         assert L.orc_sizeof_lgp_ins() == C.sizeof(LgpIns)
@@ -189,3 +191,33 @@ def lgp_eval(ins, m, X, c):
     if lib().orc_lgp_eval(ins, m, _p(X), X.shape[1], c, C.byref(r), C.byref(d), C.byref(f)) != 0:
         raise ValueError("oracle: malformed lgp")
     return np.float32(r.value), d.value, f.value
+
+
+# ---------------------------------------------------------------------------
+# Boolean trees over bit-packed cases (bit b of word w is case 32 w + b)
+# ---------------------------------------------------------------------------
+def bool_outputs(tok, off, Xw):
+    """Output words (P, W) of Boolean trees on feature-major words Xw (F, W)."""
+    tok, off = _c(tok, np.int32), _c(off, np.int64)
+    Xw = _c(Xw, np.uint32)
+    F, W = Xw.shape
+    P = len(off) - 1
+    out = np.zeros((P, W), np.uint32)
+    rc = lib().orc_bool_outputs(_p(tok), _p(off), P, _p(Xw), F, W, _p(out))
+    if rc != 0:
+        raise ValueError("malformed Boolean tree")
+    return out
+
+
+def eval_bool(tok, off, Xw, n_cases, yw):
+    """Hit counts (int64[P]) of Boolean trees: cases whose output bit equals
+    the target bit, counted case by case."""
+    tok, off = _c(tok, np.int32), _c(off, np.int64)
+    Xw, yw = _c(Xw, np.uint32), _c(yw, np.uint32)
+    F = Xw.shape[0]
+    P = len(off) - 1
+    hits = np.zeros(P, np.int64)
+    rc = lib().orc_bool_hits(_p(tok), _p(off), P, _p(Xw), F, int(n_cases), _p(yw), _p(hits))
+    if rc != 0:
+        raise ValueError("malformed Boolean tree")
+    return hits

@@ -25,7 +25,10 @@
  *     top of the stack S, with results always pushed; produced from RPN by a
  *     symbolic stack (section 5);
  *   - register linear GP programs (dst, op, src1, src2), the register-based
- *     linear form of Brameier and Banzhaf the paper cites in section 5.
+ *     linear form of Brameier and Banzhaf the paper cites in section 5;
+ *   - Boolean trees over {AND, OR, NAND, NOR} on bit-packed cases, 32 per
+ *     machine word (sub-machine-code GP, sections 3 and 4.2), with the hit
+ *     count checked bit by bit.
  *
  * Operator semantics (IEEE binary32, round to nearest even, no contraction,
  * denormals kept).  The paper names the functions but not their protection;
@@ -519,3 +522,94 @@ float orc_apply(int op, float a, float b)
 }
 
 int orc_sizeof_lgp_ins(void) { return (int)sizeof(orc_lgp_ins); }
+
+/* ------------------------------------------------------------------------ */
+/* Boolean trees over bit-packed cases (the multiplexer problem, sections 3  */
+/* and 4.2: sub-machine-code GP evaluates 32 cases per machine word)         */
+/* ------------------------------------------------------------------------ */
+/* Functions AND, OR, NAND, NOR of two inputs; terminals are the inputs.
+ * Case c is bit (c mod 32) of word (c div 32): X[f * W + w] holds input f for
+ * cases 32w .. 32w + 31.  A bitwise function of two words is the function of
+ * the two inputs for each of the 32 cases, so evaluating a tree on a word
+ * evaluates it on 32 cases at once. */
+enum { O_AND = 8, O_OR = 9, O_NAND = 10, O_NOR = 11 };
+
+static int bool_arity(int op)
+{
+    switch (op) {
+    case O_AND: case O_OR: case O_NAND: case O_NOR: return 2;
+    case O_VAR: return 0;
+    default: return -1;
+    }
+}
+
+static int check_bool_tree(const int32_t* tok, int64_t n, int32_t F)
+{
+    int64_t need = 1;
+    if (n <= 0) return ORC_BAD;
+    for (int64_t i = 0; i < n; i++) {
+        int a = bool_arity(tok[i] & 0xFF);
+        if (a < 0 || need <= 0) return ORC_BAD;
+        if (a == 0 && (int64_t)((uint32_t)tok[i] >> 8) >= F) return ORC_BAD;
+        need += a - 1;
+    }
+    return need == 0 ? ORC_OK : ORC_BAD;
+}
+
+/* Recursive prefix interpreter on one word of 32 cases. */
+static uint32_t eval_bool_prefix(const int32_t* tok, int64_t* i, const uint32_t* X, int64_t W, int64_t w)
+{
+    int32_t t = tok[*i];
+    int op = t & 0xFF;
+    (*i)++;
+    if (op == O_VAR) return X[(int64_t)((uint32_t)t >> 8) * W + w];
+    uint32_t a = eval_bool_prefix(tok, i, X, W, w);
+    uint32_t b = eval_bool_prefix(tok, i, X, W, w);
+    switch (op) {
+    case O_AND: return a & b;
+    case O_OR: return a | b;
+    case O_NAND: return ~(a & b);
+    default: return ~(a | b);      /* O_NOR */
+    }
+}
+
+/* out[p*W + w] = word w of tree p's outputs, W = ceil(n_cases / 32) */
+int orc_bool_outputs(const int32_t* tok, const int64_t* off, int32_t P, const uint32_t* X, int32_t F,
+                     int64_t W, uint32_t* out)
+{
+    for (int32_t p = 0; p < P; p++) {
+        const int32_t* t = tok + off[p];
+        int64_t n = off[p + 1] - off[p];
+        if (check_bool_tree(t, n, F) != ORC_OK) return ORC_BAD;
+        for (int64_t w = 0; w < W; w++) {
+            int64_t i = 0;
+            out[(int64_t)p * W + w] = eval_bool_prefix(t, &i, X, W, w);
+        }
+    }
+    return ORC_OK;
+}
+
+/* hits[p] = number of cases c < n_cases whose output bit equals y's bit,
+ * counted case by case. */
+int orc_bool_hits(const int32_t* tok, const int64_t* off, int32_t P, const uint32_t* X, int32_t F,
+                  int64_t n_cases, const uint32_t* y, int64_t* hits)
+{
+    const int64_t W = (n_cases + 31) / 32;
+    for (int32_t p = 0; p < P; p++) {
+        const int32_t* t = tok + off[p];
+        int64_t n = off[p + 1] - off[p];
+        if (check_bool_tree(t, n, F) != ORC_OK) return ORC_BAD;
+        int64_t h = 0;
+        for (int64_t w = 0; w < W; w++) {
+            int64_t i = 0;
+            uint32_t o = eval_bool_prefix(t, &i, X, W, w);
+            for (int b = 0; b < 32; b++) {
+                int64_t c = 32 * w + b;
+                if (c >= n_cases) break;
+                if (((o >> b) & 1u) == ((y[w] >> b) & 1u)) h++;
+            }
+        }
+        hits[p] = h;
+    }
+    return ORC_OK;
+}

@@ -57,9 +57,11 @@ def lib():
         sig = {
             "gp_eval_tree": [P, P, P, i32, P, i32, i64, P, i32, P, P],
             "gp_eval_tree_1d": [P, P, P, i32, P, i32, i64, P, i32, i32, P, P],
+            "gp_eval_bool": [P, P, i32, P, i32, i64, P, i32, P, P],
             "gp_eval_linear": [P, P, P, P, i32, i32, P, i32, i64, P, i32, P, P],
             "gp_progset_tree": [P, P, P, i32, i32, P, P],
             "gp_progset_linear": [P, P, P, P, i32, i32, i32, P, P],
+            "gp_progset_bool": [P, P, i32, i32, P, P],
             "gp_progset_eval": [P, P, i32, i64, P, i32, P, P],
             "gp_progset_get_info": [P, P],
             "gp_progset_destroy": [P],
@@ -148,6 +150,18 @@ def gp_eval_tree(tok, cst, off, X, y, kind, out, n_feat=None, stream=None):
                              kind_id(kind), dptr(out), stream_ptr(stream)))
 
 
+def gp_eval_bool(tok, off, X, y, kind, out, n_cases, n_feat=None, stream=None):
+    """Boolean trees over bit-packed cases.  X: (F, n_words) int32/uint32
+    device tensor (bit b of word w is case 32 w + b); y: (n_words,) device
+    tensor or None for kind "cases"; out: int32[P] (hits) or int32[P,
+    n_words] (output words)."""
+    tok, tp = _np(tok, np.int32)
+    off, op = _np(off, np.int64)
+    F = int(X.shape[0])
+    check(lib().gp_eval_bool(tp, op, len(off) - 1, dptr(X), n_feat or F, int(n_cases), dptr(y), kind_id(kind),
+                             dptr(out), stream_ptr(stream)))
+
+
 GP_1D_FORMS = {"rpn": 0, "lgp": 1}
 
 
@@ -202,8 +216,19 @@ class ProgSet:
                                       C.byref(h)))
         return cls(h)
 
-    def eval(self, X, y, kind, out, stream=None):
-        check(lib().gp_progset_eval(self._h, dptr(X), int(X.shape[0]), int(X.shape[1]), dptr(y),
+    @classmethod
+    def boolean(cls, tok, off, n_feat, stream=None):
+        """Boolean trees (gp_progset_bool); eval then takes uint32 words and n_cases in bits."""
+        tok, tp = _np(tok, np.int32)
+        off, op = _np(off, np.int64)
+        h = C.c_void_p()
+        check(lib().gp_progset_bool(tp, op, len(off) - 1, n_feat, stream_ptr(stream), C.byref(h)))
+        return cls(h)
+
+    def eval(self, X, y, kind, out, stream=None, n_cases=None):
+        """n_cases: defaults to X.shape[1]; a Boolean set needs the bit count."""
+        n = int(X.shape[1]) if n_cases is None else int(n_cases)
+        check(lib().gp_progset_eval(self._h, dptr(X), int(X.shape[0]), n, dptr(y),
                                     kind_id(kind), dptr(out), stream_ptr(stream)))
 
     def info(self) -> dict:
@@ -350,9 +375,11 @@ def variants():
     for i in range(L.gp_num_variants()):
         t, d, f, v, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f), C.byref(v), C.byref(fl)))
-        arith = bool(fl.value & 1)
+        arith, boolean = bool(fl.value & 1), bool(fl.value & 2)
+        suffix = "_b" if boolean else ("_a" if arith else "")
         out.append({"t": t.value, "depth": d.value, "n_feat": f.value, "vgprs": v.value, "no_transc": arith,
-                    "kernel": "k_core_%d_%d_%d_%d%s" % (t.value, d.value, f.value, v.value, "_a" if arith else "")})
+                    "boolean": boolean,
+                    "kernel": "k_core_%d_%d_%d_%d%s" % (t.value, d.value, f.value, v.value, suffix)})
     return out
 
 

@@ -20,6 +20,11 @@
 // per (program, block), then a fixed-order reduction over blocks -- the
 // result does not depend on the tile width, the grouping, or what else
 // shared the launch.
+//
+// Kernel modes: 0 with the sin/cos/exp/log code, 1 without it (arithmetic
+// programs), 2 the Boolean function set, whose slots are 32-bit words of
+// bit-packed cases (32 cases per slot; a 256-slot block holds 8192 cases)
+// and whose fitness is the number of output bits equal to the target bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -96,7 +101,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One work unit: a case tile and the programs order[q0 .. q1).  The kernel
 // has exactly one call site of the core (its labels are unique); in probe
 // mode the core only reports where its handler table starts.
-template <int T, int D, int NF, int V0, bool AR>
+template <int T, int D, int NF, int V0, int MODE>
 __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, const float* y, int64_t N,
                                              int32_t n_load, int32_t kind, uint64_t pbase, uint32_t tile,
                                              uint32_t q0, uint32_t q1, const double* tab) {
@@ -136,7 +141,7 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             uint64_t table;
             uint32_t probe = a.probe;
             asm volatile("" : "+s"(probe));
-            Core<T, D, NF, V0>::run(code, off, pay, cst, probe, pf_end, table);
+            Core<T, D, NF, V0, MODE == 2>::run(code, off, pay, cst, probe, pf_end, table);
             // later passes skip the prefetch; an opaque 0, so the first pass is not peeled off
             pf_end = 0u;
             asm volatile("" : "+s"(pf_end));
@@ -146,7 +151,8 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             }
             more = ((pay >> 24) & 15u) != CORE_OP_END;
             if (more) {
-                do_exit<T, V0, AR>(pay, cst, tab);
+                // Boolean programs never leave the core before their end
+                if constexpr (MODE != 2) do_exit<T, V0, MODE != 0>(pay, cst, tab);
                 off += 16u;
             }
         }
@@ -165,7 +171,21 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
 #pragma unroll
         for (int k = 0; k < T / 4; k++) {
             double v;
-            if (kind == GP_FIT_HITS) {
+            if constexpr (MODE == 2) {
+                // slot j of this lane is word tile0 + 64 j + lane: count its
+                // output bits equal to the target's, up to case n_bits
+                uint32_t eq = 0;
+#pragma unroll
+                for (int j = 4 * k; j < 4 * k + 4; j++) {
+                    const int64_t wd = tile0 + 64 * j + (int64_t)lane;
+                    const bool ok = 64 * j + (int64_t)lane < left;
+                    const uint32_t yw = ok ? __float_as_uint(yt[64 * j + lane]) : 0u;
+                    const int64_t bits = a.n_bits - 32 * wd;
+                    const uint32_t mask = bits >= 32 ? 0xFFFFFFFFu : (bits > 0 ? (1u << bits) - 1u : 0u);
+                    eq += ok ? (uint32_t)__popc(~(__float_as_uint(o[j]) ^ yw) & mask) : 0u;
+                }
+                v = wave_sum((double)eq);
+            } else if (kind == GP_FIT_HITS) {
                 uint32_t hits = 0;
 #pragma unroll
                 for (int j = 4 * k; j < 4 * k + 4; j++) {
@@ -202,11 +222,11 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
 // chunk * tiles_per_wave + i, i = 0 .. tiles_per_wave - 1.  The four waves of
 // a block work on the same tiles with different instruction streams, so
 // their scalar-cache misses do not fall on the same cycles.
-template <int T, int D, int NF, int V0, bool AR>
+template <int T, int D, int NF, int V0, int MODE>
 __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
     // the transcendentals' reduction tables, copied into LDS by the whole block
     const double* tab = nullptr;
-    if constexpr (!AR) {
+    if constexpr (MODE == 0) {
         __shared__ double s_tab[gmath::kTabSize];
         gmath::tab_fill(s_tab, (int)threadIdx.x, (int)blockDim.x);
         __syncthreads();
@@ -225,8 +245,16 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
         u = (b & 7u) * (nb >> 3) + (b >> 3);
         if (!a.probe) {
             if (u >= (uint32_t)a.n_units) return;
-            grp = (u / (uint32_t)a.chunks) * 4u + wib;
-            chunk = u % (uint32_t)a.chunks;
+            if (a.same_group) {
+                // wave w of the block runs group u div q on chunk 4 (u mod q) + w, q = chunks / 4 rounded up
+                const uint32_t q = ((uint32_t)a.chunks + 3u) / 4u;
+                grp = u / q;
+                chunk = (u % q) * 4u + wib;
+                if (chunk >= (uint32_t)a.chunks) return;
+            } else {
+                grp = (u / (uint32_t)a.chunks) * 4u + wib;
+                chunk = u % (uint32_t)a.chunks;
+            }
             if (grp >= (uint32_t)a.n_groups) return;
         }
     }
@@ -271,7 +299,7 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
             kind = jd.kind;
             pbase = jd.part_base;
         }
-        process_unit<T, D, NF, V0, AR>(a, X, y, N, n_load, kind, pbase, __builtin_amdgcn_readfirstlane(tile),
+        process_unit<T, D, NF, V0, MODE>(a, X, y, N, n_load, kind, pbase, __builtin_amdgcn_readfirstlane(tile),
                                __builtin_amdgcn_readfirstlane(q0), __builtin_amdgcn_readfirstlane(q1), tab);
         if (a.probe) return;
     }
@@ -279,12 +307,12 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
 
 // One kernel per variant.  amdgpu_num_vgpr(n) lets the compiler allocate 2n
 // VGPRs on gfx950 (checked at build time against the compiler's
-// reserved-register report); the core owns v[V0 ...].  AR: no sin/cos/exp/log
-// code (for programs without them).
-#define GPX_KERNEL(T, D, NF, V0, AR, NAME)                                                              \
+// reserved-register report); the core owns v[V0 ...].  MODE: 0 full, 1 no
+// sin/cos/exp/log code (for programs without them), 2 Boolean.
+#define GPX_KERNEL(T, D, NF, V0, MODE, NAME)                                                            \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr((V0) / 2))) void                   \
         k_core_##NAME(CoreArgs a) {                                                                     \
-        k_core_body<T, D, NF, V0, (AR) != 0>(a);                                                        \
+        k_core_body<T, D, NF, V0, (MODE)>(a);                                                           \
     }
 
 }  // namespace gpx

@@ -41,7 +41,7 @@ const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
 int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
 int core_reg_levels(int vi) { return kCoreVariants[vi].d > GPX_LIN_REGS ? kCoreVariants[vi].d : GPX_LIN_REGS; }
 
-int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc) {
+int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean) {
     // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
     // outside the core) run best with room for that code (no spills) and as
     // many waves per SIMD as that leaves, to hide its latency; the others with
@@ -58,10 +58,16 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
         if (heavy) return (v.ncv >= 64) * 100000000 + waves(v) * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
         return v.arith * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
     };
+    // Boolean programs: the most slots in flight per SIMD (waves x tile width)
+    auto score_bool = [&](const CoreVariantDesc& v) { return waves(v) * v.t * 1000 - v.nf; };
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
+        if ((v.arith == 2) != boolean) continue;
         if (v.nf < n_load || v.d < depth || (v.arith && has_transc)) continue;
-        if (best < 0 || score(v) > score(kCoreVariants[best])) best = i;
+        if (best < 0) { best = i; continue; }
+        const bool better = boolean ? score_bool(v) > score_bool(kCoreVariants[best])
+                                    : score(v) > score(kCoreVariants[best]);
+        if (better) best = i;
     }
     return best;
 }
@@ -137,7 +143,9 @@ struct Emitter {
     }
 };
 
-bool is_core_op(uint32_t op) { return op == GP_ADD || op == GP_SUB || op == GP_MUL; }
+bool is_core_op(uint32_t op) {
+    return op == GP_ADD || op == GP_SUB || op == GP_MUL || (op >= GP_AND && op <= GP_NOR);
+}
 
 }  // namespace
 
@@ -185,7 +193,7 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
                     else e.put(CK_CS, op, 0, 0, (uint32_t)((h - 1) * T), c);
                     break;
                 case M_XX:
-                    if (v.nf <= 8) {
+                    if (v.nf <= 8 && v.arith != 2) {
                         if (comm) {
                             const int a = fa < fb ? fa : fb, b = fa < fb ? fb : fa;
                             e.put(CK_XX, op, h, b - a, (uint32_t)(a * T), 0);
@@ -332,6 +340,7 @@ int core_variant_t(int vi) { return kCoreVariants[vi].t; }
 int core_variant_ncv(int vi) { return kCoreVariants[vi].ncv; }
 int core_variant_d(int vi) { return kCoreVariants[vi].d; }
 int core_variant_nf(int vi) { return kCoreVariants[vi].nf; }
-int core_variant_arith(int vi) { return kCoreVariants[vi].arith; }
+int core_variant_arith(int vi) { return kCoreVariants[vi].arith != 0; }
+bool core_variant_bool(int vi) { return kCoreVariants[vi].arith == 2; }
 
 }  // namespace gpx

@@ -67,6 +67,8 @@ struct CoreArgs {
     int32_t chunks;
     int32_t prefetch;           // burst-load each program's code into the scalar cache first
     int32_t n_groups;           // program groups (implicit units)
+    int32_t same_group;         // implicit units: the four waves of a block run one group on four chunks
+    int64_t n_bits;             // Boolean kernels: cases (bits) in the N words of each row
     uint32_t probe;             // nonzero: write the handler table address and return
     double* partials;
     float* cases_out;

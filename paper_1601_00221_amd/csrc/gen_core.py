@@ -43,12 +43,14 @@ import sys
 SLOT = 64                 # bytes per handler slot; longer handlers take several
 LIN_REGS = 8              # register slots reserved for linear programs (and stack levels)
 
-# (T, D, NF, NCV, AR) variants: T case slots per lane, D stack levels, NF
+# (T, D, NF, NCV, MODE) variants: T case slots per lane, D stack levels, NF
 # feature slots, NCV VGPRs left to the compiler (the core owns v[NCV ...]),
-# AR = 1 for a kernel without the sin/cos/exp/log code (for programs that use
-# none; its compiled part is small, so nothing spills).  Work that leaves the
-# core (sin/cos/exp/log in binary64, protected division) runs in the
-# compiler's VGPRs: programs rich in it take a variant with room for it.
+# MODE = 0 for the arithmetic function set with the sin/cos/exp/log code,
+# 1 without that code (for programs that use none; its compiled part is
+# small, so nothing spills), 2 for the Boolean function set (slots are
+# 32-bit words of bit-packed cases).  Work that leaves the core (sin/cos/
+# exp/log in binary64, protected division) runs in the compiler's VGPRs:
+# programs rich in it take a variant with room for it.
 VARIANTS = [
     (8, 6, 8, 40, 0),
     (8, 6, 8, 128, 0),
@@ -66,15 +68,23 @@ VARIANTS = [
     (8, 8, 8, 40, 1),
     (4, 8, 16, 40, 1),
     (4, 12, 32, 40, 1),
+    (8, 8, 20, 32, 2),
+    (4, 12, 32, 40, 2),
 ]
 
 
 def vname(v):
-    """Kernel name suffix of a variant: T_D_NF_NCV, plus _a when it has no sin/cos/exp/log code."""
-    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], "_a" if v[4] else "")
+    """Kernel name suffix of a variant: T_D_NF_NCV, plus _a when it has no
+    sin/cos/exp/log code and _b for the Boolean function set."""
+    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], ("", "_a", "_b")[v[4]])
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
 OP_ID = {"add": 0, "sub": 1, "mul": 2}
+# Boolean functions (ids as the tree opcodes GP_AND .. GP_NOR): one bitwise
+# operation, then a NOT for NAND and NOR
+BOOL_OPS = {"and": ("v_and_b32_e32", False), "or": ("v_or_b32_e32", False),
+            "nand": ("v_and_b32_e32", True), "nor": ("v_or_b32_e32", True)}
+BOOL_ID = {"and": 8, "or": 9, "nand": 10, "nor": 11}
 
 # handler kinds (keep in sync with the generated enum below)
 KINDS = ["EXIT", "SS", "SSR", "SX", "XS", "SC", "CS", "XX", "XX2", "XC", "CX", "PUSHX", "PUSHC",
@@ -98,13 +108,13 @@ class Handler:
         self.size += nbytes
 
 
-def gen_variant(T, D, NF, NCV):
+def gen_variant(T, D, NF, NCV, mode=0):
     V0 = NCV
     FO = max(LIN_REGS, D) * T          # register/stack block, then the features
     assert FO + NF * T <= 256, "index range exceeds 8 bits"
     assert V0 + FO + NF * T <= 256
     assert NCV % 8 == 0
-    tag = "T%dD%dF%dV%d" % (T, D, NF, NCV)
+    tag = "T%dD%dF%dV%d%s" % (T, D, NF, NCV, "B" if mode == 2 else "")
     hs = []
 
     def prologue(h, const=False, second_index=False, index=None):
@@ -140,6 +150,10 @@ def gen_variant(T, D, NF, NCV):
     h.emit("s_set_gpr_idx_off", 4)
     h.emit("s_branch .Lgpx_end_%s" % tag, 4)
     hs.append(h)
+
+    if mode == 2:
+        bool_handlers(hs, T, D, V0, FO, prologue, idx_on, epilogue, valu)
+        return finish(hs, tag, V0, FO)
 
     # ---------------------------------------------------------------- trees
     for op in ("add", "sub", "mul"):
@@ -302,10 +316,66 @@ def gen_variant(T, D, NF, NCV):
         epilogue(h)
         hs.append(h)
 
-    # ---------------------------------------------------------------- phases
-    hs = [phase_a(h, tag) for h in hs] + [phase_b(h, tag) for h in hs]
+    return finish(hs, tag, V0, FO)
 
-    # ---------------------------------------------------------------- layout
+
+def bool_handlers(hs, T, D, V0, FO, prologue, idx_on, epilogue, valu):
+    """Handlers of the Boolean function set.  Every function is symmetric, so
+    only the forms with the stack (or first) operand on the left exist: SS,
+    SX, XX2 (two features, two passes) and PUSHX.  NAND and NOR complement
+    the result with v_not_b32, whose source is never an indexed operand."""
+    for op, (ins, neg) in BOOL_OPS.items():
+        h = Handler(K["SS"], BOOL_ID[op])           # s[h-2] = s[h-2] op s[h-1]; index (h-2)*T
+        prologue(h, index=["SRC0", "SRC1", "DST"])
+        for j in range(T):
+            valu(h, "%s %s, %s, %s" % (ins, vr(V0 + j), vr(V0 + j), vr(V0 + T + j)))
+        if neg:                                     # source and destination share the index
+            for j in range(T):
+                valu(h, "v_not_b32_e32 %s, %s" % (vr(V0 + j), vr(V0 + j)))
+        epilogue(h)
+        hs.append(h)
+    for op, (ins, neg) in BOOL_OPS.items():
+        for l in range(D):
+            h = Handler(K["SX"], BOOL_ID[op], l)    # s[l] = s[l] op x[b]; index = feature offset
+            prologue(h, index=["SRC1"])
+            for j in range(T):
+                r = vr(V0 + l * T + j)
+                valu(h, "%s %s, %s, %s" % (ins, r, r, vr(V0 + j)))
+            if neg:                                 # only SRC1 is indexed
+                for j in range(T):
+                    r = vr(V0 + l * T + j)
+                    valu(h, "v_not_b32_e32 %s, %s" % (r, r))
+            epilogue(h)
+            hs.append(h)
+    for op, (ins, neg) in BOOL_OPS.items():
+        for l in range(D):
+            h = Handler(K["XX2"], BOOL_ID[op], l)   # s[l] = x[b]; s[l] = x[a] op s[l]
+            prologue(h, second_index=True)
+            idx_on(h, "s71", ["SRC0"])
+            for j in range(T):
+                valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + l * T + j), vr(V0 + j)))
+            idx_on(h, "s70", ["SRC0"])
+            for j in range(T):
+                r = vr(V0 + l * T + j)
+                valu(h, "%s %s, %s, %s" % (ins, r, vr(V0 + j), r))
+            if neg:                                 # the NOT reads s[l] itself: index off
+                h.emit("s_set_gpr_idx_off", 4)
+                for j in range(T):
+                    r = vr(V0 + l * T + j)
+                    valu(h, "v_not_b32_e32 %s, %s" % (r, r))
+            epilogue(h)
+            hs.append(h)
+    h = Handler(K["PUSHX"])                         # s[0] = x[a] (a program that is one variable)
+    prologue(h, index=["SRC0"])
+    for j in range(T):
+        valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + j), vr(V0 + j)))
+    epilogue(h)
+    hs.append(h)
+
+
+def finish(hs, tag, V0, FO):
+    """Both phases of every handler, laid out in 64-byte slots."""
+    hs = [phase_a(h, tag) for h in hs] + [phase_b(h, tag) for h in hs]
     slot = 0
     for h in hs:
         h.slot = slot
@@ -465,7 +535,7 @@ def main(out_dir):
     lines.append(" \\\n".join("    X(%d, %d, %d, %d, %d)" % v for v in VARIANTS))
     lines.append("")
     clob_s = ", ".join('"s%d"' % n for n in (63, 64, 65, 66, 67, 70, 71, 72, 76, 77))
-    lines.append("template <int T, int D, int NF, int V0> struct Core;")
+    lines.append("template <int T, int D, int NF, int V0, bool B> struct Core;")
     lines.append("template <int T, int V0> __device__ void core_gather(uint32_t off, float (&v)[T]);")
     lines.append("template <int T, int V0> __device__ void core_scatter(uint32_t off, const float (&v)[T]);")
     for T, V0 in sorted(set((v[0], v[3]) for v in VARIANTS)):
@@ -473,15 +543,16 @@ def main(out_dir):
     host = []
     seen = {}
     for (T, D, NF, NCV, AR) in VARIANTS:
-        if (T, D, NF, NCV) in seen:       # same core as another variant
-            host.append((T, D, NF, NCV, AR) + seen[(T, D, NF, NCV)])
+        B = AR == 2
+        if (T, D, NF, NCV, B) in seen:    # same core as another variant
+            host.append((T, D, NF, NCV, AR) + seen[(T, D, NF, NCV, B)])
             continue
-        tag, V0, FO, hs, nslots = gen_variant(T, D, NF, NCV)
-        seen[(T, D, NF, NCV)] = (tag, hs, nslots)
+        tag, V0, FO, hs, nslots = gen_variant(T, D, NF, NCV, AR)
+        seen[(T, D, NF, NCV, B)] = (tag, hs, nslots)
         text = asm_text(T, D, NF, tag, hs)
         clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
         assert NCV + FO + NF * T <= 256
-        lines.append("template <> struct Core<%d, %d, %d, %d> {" % (T, D, NF, NCV))
+        lines.append("template <> struct Core<%d, %d, %d, %d, %s> {" % (T, D, NF, NCV, "true" if B else "false"))
         lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")
         lines.append("    // pf_end: byte offset where the program ends (its code is first burst-loaded into the")
         lines.append("    // scalar cache), or 0")
@@ -544,7 +615,7 @@ def main(out_dir):
                 % ", ".join("core_occupancy_" + n for n in names))
     write_if_changed(os.path.join(out_dir, "core_dispatch.inc"), "\n".join(disp) + "\n")
     for (T, D, NF, NCV, AR, tag, hs, nslots) in host:
-        print("%s%s: %d handlers, %d slots (%d KiB)" % (tag, "a" if AR else "", len(hs), nslots, nslots * SLOT // 1024))
+        print("%s%s: %d handlers, %d slots (%d KiB)" % (tag, "a" if AR == 1 else "", len(hs), nslots, nslots * SLOT // 1024))
     return path
 
 

@@ -10,7 +10,7 @@ namespace gpx {
 // (the paper's linear form, section 5): each function reads its operands
 // from a case input X, a constant C or the stack S and pushes its result.
 // Two 32-bit words per instruction:
-//   w0 bits 0-3   op    (GP function 0-7, or OP_PUSH)
+//   w0 bits 0-3   op    (GP function 0-11, or OP_PUSH)
 //      bits 4-7   mode  (where the operands come from, see below)
 //      bits 8-15  feature index of operand A (X modes)
 //      bits 16-23 feature index of operand B (X modes)
@@ -18,7 +18,7 @@ namespace gpx {
 //   w1            constant operand, binary32 bits (C modes)
 // h is the stack height before the instruction; s[0] is the bottom.
 // ---------------------------------------------------------------------------
-enum : uint32_t { OP_PUSH = 8 };
+enum : uint32_t { OP_PUSH = 15 };
 
 enum : uint32_t {
     M_SS = 0,   // A = s[h-2], B = s[h-1]  -> s[h-2], h-1
@@ -68,11 +68,17 @@ struct TreeLowering {
     int32_t n_reversed = 0;
 };
 
+// Function sets a tree may use: the arithmetic set {+,-,*,/p,sin,cos,exp,log}
+// with variables and constants, or the Boolean set {AND,OR,NAND,NOR} with
+// variables only.
+enum : int { OPSET_REAL = 0, OPSET_BOOL = 1 };
+
 // Validates one prefix tree and appends its lowered words to `out` (may be
 // null to only compute the statistics).  Returns 0 or a gp_status code and
-// writes a message into `err` (at least 256 bytes).
+// writes a message into `err` (at least 256 bytes).  cst may be null for
+// the Boolean set.
 int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat,
-               uint32_t* out, TreeLowering* st, char* err);
+               uint32_t* out, TreeLowering* st, char* err, int opset = OPSET_REAL);
 
 // Validates one register linear program.
 int check_linear(const uint32_t* code, int64_t n, int64_t n_cst, int32_t n_reg, int32_t n_feat,

@@ -22,7 +22,14 @@
 
 namespace gpx {
 
-static int arity_of(int op) {
+static int arity_of(int op, int opset = OPSET_REAL) {
+    if (opset == OPSET_BOOL) {
+        switch (op) {
+            case GP_AND: case GP_OR: case GP_NAND: case GP_NOR: return 2;
+            case GP_VAR: return 0;
+            default: return -1;
+        }
+    }
     switch (op) {
         case GP_ADD: case GP_SUB: case GP_MUL: case GP_PDIV: return 2;
         case GP_SIN: case GP_COS: case GP_EXPC: case GP_PLOG: return 1;
@@ -31,7 +38,8 @@ static int arity_of(int op) {
     }
 }
 
-static bool commutative(int op) { return op == GP_ADD || op == GP_MUL; }
+// the four Boolean functions are symmetric, like + and *
+static bool commutative(int op) { return op == GP_ADD || op == GP_MUL || (op >= GP_AND && op <= GP_NOR); }
 
 static uint32_t fbits(float f) {
     uint32_t u;
@@ -40,7 +48,7 @@ static uint32_t fbits(float f) {
 }
 
 int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, uint32_t* out,
-               TreeLowering* st, char* err) {
+               TreeLowering* st, char* err, int opset) {
     TreeLowering s;
     if (n < 1) {
         snprintf(err, 256, "empty program");
@@ -58,9 +66,10 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
     open.reserve(64);
     for (int32_t i = 0; i < N; i++) {
         const int op = tok[i] & 0xFF;
-        const int a = arity_of(op);
+        const int a = arity_of(op, opset);
         if (a < 0) {
-            snprintf(err, 256, "token %d: unknown opcode %d", i, op);
+            snprintf(err, 256, "token %d: opcode %d is not in the %s function set", i, op,
+                     opset == OPSET_BOOL ? "Boolean" : "arithmetic");
             return GP_E_INVAL;
         }
         if (op == GP_VAR) {

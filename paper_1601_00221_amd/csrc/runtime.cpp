@@ -134,12 +134,13 @@ static uint32_t op_cost(uint32_t op) {
 }
 
 gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t P,
-                     int32_t n_feat, ProgData& pd) {
+                     int32_t n_feat, ProgData& pd, int opset) {
     if (P < 0) return fail(GP_E_INVAL, "n_prog < 0");
-    if (P > 0 && (!tok || !cst || !off)) return fail(GP_E_INVAL, "null program array");
+    if (P > 0 && (!tok || (!cst && opset != OPSET_BOOL) || !off)) return fail(GP_E_INVAL, "null program array");
     if (n_feat < 1) return fail(GP_E_INVAL, "n_feat < 1");
     pd = ProgData();
     pd.form = FORM_TREE;
+    pd.opset = opset;
     pd.n_prog = P;
     pd.n_feat = n_feat;
     if (P == 0) return GP_OK;
@@ -160,7 +161,8 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
     for (int32_t p = 0; p < P; p++) {
         const int64_t n = off[p + 1] - off[p];
         TreeLowering st;
-        int rc = lower_tree(tok + off[p], cst + off[p], n, n_feat, pd.code.data() + 2 * w, &st, err);
+        int rc = lower_tree(tok + off[p], cst ? cst + off[p] : nullptr, n, n_feat, pd.code.data() + 2 * w, &st, err,
+                            opset);
         if (rc != GP_OK) return fail((gp_status)rc, "program %d: %s", p, err);
         for (int64_t i = 0; i < n; i++) {
             const int32_t t = tok[off[p] + i];
@@ -396,7 +398,7 @@ hipError_t timed_launch_end(hipStream_t s, int slot) {
 
 gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
                     int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
-                    const EvalOptions* opt) {
+                    const EvalOptions* opt, int64_t n_bits) {
     if (!X) return fail(GP_E_INVAL, "X is null");
     if (!out) return fail(GP_E_INVAL, "out is null");
     if (N < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
@@ -406,14 +408,18 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     if (pd.n_prog == 0) return GP_OK;
     if (pd.n_load > GP_MAX_FEAT)
         return fail(GP_E_INVAL, "programs read feature %d; at most %d features are supported", pd.n_load - 1, GP_MAX_FEAT);
+    const bool boolean = pd.opset == OPSET_BOOL;
+    if (boolean != (n_bits > 0)) return fail(GP_E_INVAL, "internal: Boolean programs need a bit count");
+    if (boolean && kind != GP_FIT_HITS && kind != GP_OUT_CASES)
+        return fail(GP_E_INVAL, "Boolean programs take GP_FIT_HITS or GP_OUT_CASES, not kind %d", kind);
     const int vi = opt && opt->variant >= 0
                        ? opt->variant
                        : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0,
-                                           pd.n_transc > 0);
+                                           pd.n_transc > 0, boolean);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth ||
-        (core_variant_arith(vi) && pd.n_transc > 0))
+        (core_variant_arith(vi) && pd.n_transc > 0) || core_variant_bool(vi) != boolean)
         return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
     gp_status st;
     if ((st = core_ready(vi, s)) != GP_OK) return st;
@@ -426,7 +432,8 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     const int32_t tiles = (int32_t)tiles64;
     const LaunchShape L = launch_shape(pd, tiles, opt);
     const int32_t G = L.G;
-    const int64_t units = (int64_t)L.chunks * ((G + 3) / 4);
+    const int32_t same_group = env_int("GP2D_SAME_GROUP", 0) > 0 ? 1 : 0;
+    const int64_t units = same_group ? (int64_t)G * ((L.chunks + 3) / 4) : (int64_t)L.chunks * ((G + 3) / 4);
     if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
     const uint32_t *order, *goff;
     if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
@@ -451,6 +458,8 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     a.chunks = L.chunks;
     a.prefetch = code_prefetch();
     a.n_groups = G;
+    a.same_group = same_group;
+    a.n_bits = n_bits;
     a.partials = (double*)w.partials.p;
     a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
     uint32_t blocks = (uint32_t)units;
@@ -520,6 +529,25 @@ gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* 
     return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
 }
 
+gp_status gp_eval_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, const uint32_t* X, int32_t n_feat,
+                       int64_t n_cases, const uint32_t* y, int32_t kind, void* out, void* stream) {
+    clear_error();
+    if (n_cases < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
+    if (n_cases > 0x7FFFFFFF) return fail(GP_E_INVAL, "n_cases above 2^31 - 1 (hit counts are int32)");
+    if (kind != GP_FIT_HITS && kind != GP_OUT_CASES)
+        return fail(GP_E_INVAL, "Boolean programs take GP_FIT_HITS or GP_OUT_CASES, not kind %d", kind);
+    ProgData pd;
+    gp_status st = build_tree(tok, nullptr, off, n_prog, n_feat, pd, OPSET_BOOL);
+    if (st != GP_OK || n_prog == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace& w = workspace(s);
+    std::lock_guard<std::mutex> g(w.mu);
+    // one slot per 32-bit word: the kernel sees n_words "cases"
+    const int64_t n_words = (n_cases + 31) / 32;
+    return eval_core(pd, w.oneshot, true, (const float*)X, n_feat, n_words, (const float*)y, kind, out, s, w,
+                     nullptr, n_cases);
+}
+
 static gp_status progset_finish(ProgData&& pd, void* stream, gp_progset** ps) {
     (void)stream;   // programs are translated and uploaded on first evaluation, per kernel variant
     std::unique_ptr<gp_progset> p(new gp_progset());
@@ -534,6 +562,16 @@ gp_status gp_progset_tree(const int32_t* tok, const float* cst, const int64_t* o
     if (!ps) return fail(GP_E_INVAL, "ps is null");
     ProgData pd;
     gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd);
+    if (st != GP_OK) return st;
+    return progset_finish(std::move(pd), stream, ps);
+}
+
+gp_status gp_progset_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, int32_t n_feat, void* stream,
+                          gp_progset** ps) {
+    clear_error();
+    if (!ps) return fail(GP_E_INVAL, "ps is null");
+    ProgData pd;
+    gp_status st = build_tree(tok, nullptr, off, n_prog, n_feat, pd, OPSET_BOOL);
     if (st != GP_OK) return st;
     return progset_finish(std::move(pd), stream, ps);
 }
@@ -557,6 +595,13 @@ gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_
     Workspace& w = workspace(s);
     std::lock_guard<std::mutex> g(w.mu);
     std::lock_guard<std::mutex> g2(ps->mu);
+    if (ps->pd.opset == OPSET_BOOL) {
+        // Boolean set: X and y are 32-bit words, n_cases counts bits
+        if (n_cases < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
+        if (n_cases > 0x7FFFFFFF) return fail(GP_E_INVAL, "n_cases above 2^31 - 1 (hit counts are int32)");
+        return eval_core(ps->pd, ps->dps, false, X, n_feat, (n_cases + 31) / 32, y, kind, out, s, w, nullptr,
+                         n_cases);
+    }
     return eval_core(ps->pd, ps->dps, false, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
 }
 
@@ -571,7 +616,7 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->n_gpop = ps->pd.n_gpop;
     info->variant = pick_core_variant(ps->pd.n_load, ps->pd.max_depth,
                                       ps->pd.n_instr ? (double)ps->pd.n_transc / ps->pd.n_instr : 0.0,
-                                      ps->pd.n_transc > 0);
+                                      ps->pd.n_transc > 0, ps->pd.opset == OPSET_BOOL);
     info->pad = 0;
     return GP_OK;
 }
@@ -606,8 +651,10 @@ gp_status gp_core_lower_tree(const int32_t* tok, const float* cst, const int64_t
                              int32_t variant, uint64_t table_base, uint32_t* words, int64_t max_words,
                              int64_t* prog_off, int64_t* n_words) {
     clear_error();
+    if (variant < 0 || variant >= core_variants()) return fail(GP_E_INVAL, "variant %d does not exist", variant);
+    // a Boolean kernel takes trees of the Boolean function set
     ProgData pd;
-    gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd);
+    gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd, core_variant_bool(variant) ? OPSET_BOOL : OPSET_REAL);
     if (st != GP_OK) return st;
     return core_lower_common(pd, variant, table_base, words, max_words, prog_off, n_words);
 }

@@ -44,6 +44,7 @@ struct Staging {
 // Lowered programs on the host.
 struct ProgData {
     int form = 0;
+    int opset = OPSET_REAL;  // function set of trees (OPSET_BOOL: Boolean, 32 cases per slot)
     int32_t n_prog = 0;
     int32_t n_feat = 0;     // declared feature count (register initialisation wraps around it)
     int32_t n_reg = 0;
@@ -97,13 +98,15 @@ hipError_t timed_launch_begin(hipStream_t s, int* slot);
 hipError_t timed_launch_end(hipStream_t s, int slot);
 
 gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, int32_t P, int32_t n_feat,
-                     ProgData& pd);
+                     ProgData& pd, int opset = OPSET_REAL);
 gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
                        int32_t P, int32_t n_reg, int32_t n_feat, ProgData& pd);
 // Evaluate lowered programs on one case matrix.  dps caches the programs
 // translated per core variant; fresh forces a new translation and upload.
+// Boolean programs (pd.opset == OPSET_BOOL) take X and y as 32-bit words, N
+// words per row, and n_bits > 0 cases; every other call passes n_bits = 0.
 gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
                     int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
-                    const EvalOptions* opt);
+                    const EvalOptions* opt, int64_t n_bits = 0);
 
 }  // namespace gpx

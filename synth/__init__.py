@@ -35,6 +35,11 @@ NAMES = {ADD: "+", SUB: "-", MUL: "*", PDIV: "/", SIN: "sin", COS: "cos",
 BASIC = (ADD, SUB, MUL, PDIV)
 FULL = (ADD, SUB, MUL, PDIV, SIN, COS, EXPC, PLOG)
 ARITH3 = (ADD, SUB, MUL)
+# Boolean function set (sub-machine-code GP: 32 bit-packed cases per word)
+AND, OR, NAND, NOR = 8, 9, 10, 11
+ARITY.update({AND: 2, OR: 2, NAND: 2, NOR: 2})
+NAMES.update({AND: "and", OR: "or", NAND: "nand", NOR: "nor"})
+BOOL_SET = (AND, OR, NAND, NOR)
 
 SRC_CONST_BASE = 128
 
@@ -540,3 +545,53 @@ def remap_features(pop, n_feat: int):
         s2 = np.where(feat, R + (s - R) % n_feat, s)
         out = (out & ~np.uint32(0xFF << sh)) | (s2.astype(np.uint32) << sh)
     return LinearPop(out.astype(np.uint32), pop.off, pop.cst, pop.cst_off, pop.n_reg)
+
+
+# ----------------------------------------------------------------------------
+# Boolean multiplexer (bit-packed, exhaustive)
+# ----------------------------------------------------------------------------
+def pack_bits(bits) -> np.ndarray:
+    """Pack a 0/1 array of cases into uint32 words: bit b of word w is case
+    32 w + b (the last word zero-padded)."""
+    bits = np.asarray(bits, np.uint8)
+    pad = (-len(bits)) % 32
+    if pad:
+        bits = np.concatenate([bits, np.zeros(pad, np.uint8)])
+    return np.packbits(bits, bitorder="little").view("<u4").astype(np.uint32)
+
+
+def mux_cases(k: int):
+    """All cases of the k-address multiplexer (k + 2^k inputs): input f of
+    case c is bit f of c; inputs 0 .. k-1 are the address bits A0 (least
+    significant) .. A(k-1), input k + d is data bit Dd; the target is the
+    data bit the address selects.  Returns (Xw (n_in, W) uint32, yw (W,)
+    uint32, n_cases)."""
+    n_in = k + (1 << k)
+    n_cases = 1 << n_in
+    c = np.arange(n_cases, dtype=np.uint64)
+    Xw = np.stack([pack_bits((c >> np.uint64(f)) & np.uint64(1)) for f in range(n_in)])
+    addr = c & np.uint64((1 << k) - 1)
+    y = (c >> (np.uint64(k) + addr)) & np.uint64(1)
+    return Xw, pack_bits(y), n_cases
+
+
+@dataclass
+class BoolWorkload:
+    name: str
+    pop: TreePop
+    Xw: np.ndarray             # (F, W) uint32
+    yw: np.ndarray             # (W,) uint32
+    n_cases: int
+    meta: dict = field(default_factory=dict)
+
+
+def mux_workload(seed: int = 6, k: int = 4, n_prog: int = 4096, max_size: int = 256) -> BoolWorkload:
+    """The 20-multiplexer (k = 4: A0-A3, D0-D15) over all 2^20 cases,
+    bit-packed into 32,768 words per input; 4096 PTC2 trees of size
+    U{1..256} over {AND, OR, NAND, NOR} with the 20 inputs as terminals;
+    fitness = number of correctly classified cases."""
+    rng = rng_for(seed)
+    Xw, yw, n_cases = mux_cases(k)
+    pop = ptc2_population(rng, n_prog, BOOL_SET, Xw.shape[0], 1, max_size, 0.0)
+    return BoolWorkload("mux%d-%dx%d" % (Xw.shape[0], n_prog, n_cases), pop, Xw, yw, n_cases,
+                        dict(k=k, n_in=Xw.shape[0]))

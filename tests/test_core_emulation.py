@@ -38,8 +38,8 @@ def f32(x):
 
 class CoreEmu:
     def __init__(self, variant_index):
-        T, D, NF, NCV = gen_core.VARIANTS[variant_index][:4]
-        tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF, NCV)
+        T, D, NF, NCV, mode = gen_core.VARIANTS[variant_index]
+        tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF, NCV, mode)
         self.T, self.D, self.NF, self.V0, self.FO = T, D, NF, V0, FO
         self.by_slot = {h.slot: h for h in hs}
         self.prog = {h.slot: [self._parse(x) for x in h.lines] for h in hs}
@@ -139,8 +139,15 @@ class CoreEmu:
         if op == "v_mov_b32_e32":
             self.v[dr] = src(*args[1], "SRC0")
             return
+        if op == "v_not_b32_e32":
+            self.v[dr] = (~src(*args[1], "SRC0").view(np.uint32)).view(np.float32)
+            return
         a = src(*args[1], "SRC0")
         b = src(*args[2], "SRC1")
+        if op in ("v_and_b32_e32", "v_or_b32_e32"):
+            ua, ub = a.view(np.uint32), b.view(np.uint32)
+            self.v[dr] = ((ua & ub) if op == "v_and_b32_e32" else (ua | ub)).view(np.float32)
+            return
         with np.errstate(all="ignore"):
             if op == "v_add_f32_e32": r = a + b
             elif op == "v_sub_f32_e32": r = a - b
@@ -204,7 +211,11 @@ def _same(a, b):
     return (a.view(np.int32) == b.view(np.int32)) | (np.isnan(a) & np.isnan(b))
 
 
-@pytest.mark.parametrize("vi", range(len(gen_core.VARIANTS)))
+REAL = [i for i, v in enumerate(gen_core.VARIANTS) if v[4] != 2]
+BOOL = [i for i, v in enumerate(gen_core.VARIANTS) if v[4] == 2]
+
+
+@pytest.mark.parametrize("vi", REAL)
 def test_core_trees_match_oracle(vi):
     T, D, NF, NCV = gen_core.VARIANTS[vi][:4]
     F = min(NF, 9)
@@ -227,7 +238,7 @@ def test_core_trees_match_oracle(vi):
         assert _same(got, ref).all()
 
 
-@pytest.mark.parametrize("vi", range(len(gen_core.VARIANTS)))
+@pytest.mark.parametrize("vi", REAL)
 def test_core_linear_match_oracle(vi):
     T, D, NF, NCV = gen_core.VARIANTS[vi][:4]
     F = min(NF, 12)
@@ -243,9 +254,31 @@ def test_core_linear_match_oracle(vi):
         assert _same(got, ref).all()
 
 
+@pytest.mark.parametrize("vi", BOOL)
+def test_core_bool_match_oracle(vi):
+    # Boolean kernels: slots are 32-bit words of bit-packed cases; the core's
+    # output words must equal the oracle's bit for bit
+    from tests import boolprogs as bp
+    T, D, NF, NCV, _ = gen_core.VARIANTS[vi]
+    F = min(NF, 20)
+    rng = synth.rng_for(500 + vi)
+    pop = synth.ptc2_population(rng, 30, synth.BOOL_SET, F, 1, 120, 0.0)
+    sol = bp.mux_solution(2)
+    x = bp.var(F - 1)
+    pop2 = bp.pop_of(sol, x, bp.NOT(x), bp.fn(synth.NOR, x, bp.var(0)), bp.fn(synth.NAND, bp.var(1), bp.var(0)))
+    W = 64 * T + 37
+    Xw = rng.integers(0, 2**32, size=(F, W), dtype=np.uint64).astype(np.uint32)
+    emu = CoreEmu(vi)
+    for pp in (pop, pop2):
+        words, prog_off = gp.core_lower(pp, F, vi, BASE)
+        got = emu.evaluate(words, prog_off, Xw.view(np.float32), F).view(np.uint32)
+        ref = oracle.bool_outputs(pp.tok, pp.off, Xw)
+        assert (got == ref).all()
+
+
 def test_every_handler_is_reachable_and_in_its_slot():
-    for vi, (T, D, NF, NCV, _) in enumerate(gen_core.VARIANTS):
-        tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF, NCV)
+    for vi, (T, D, NF, NCV, mode) in enumerate(gen_core.VARIANTS):
+        tag, V0, FO, hs, nslots = gen_core.gen_variant(T, D, NF, NCV, mode)
         slots = [h.slot for h in hs]
         assert slots == sorted(slots) and len(set(slots)) == len(slots)
         for h in hs:

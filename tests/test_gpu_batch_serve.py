@@ -198,9 +198,9 @@ def test_served_under_tight_memory_budget():
 
 
 def test_every_variant_on_arithmetic_programs():
-    """Every kernel variant, including those without sin/cos/exp/log code,
-    gives the oracle's fitness (within the fitness tolerance) on programs
-    over {+,-,*,/p}."""
+    """Every arithmetic kernel variant, including those without sin/cos/exp/log
+    code, gives the oracle's fitness (within the fitness tolerance) on
+    programs over {+,-,*,/p}; Boolean kernels refuse them."""
     import torch
     rng = synth.rng_for(41)
     F = 8
@@ -217,6 +217,11 @@ def test_every_variant_on_arithmetic_programs():
         out_t = gp.out_tensor("mse", trees.n_prog, 0)
         out_l = gp.out_tensor("mse", lin.n_prog, 0)
         jobs = [gp.make_job(trees, 0, "mse", out_t), gp.make_job(lin, 0, "mse", out_l)]
+        if v["boolean"]:
+            # Boolean kernels take only Boolean trees, and never batched
+            with pytest.raises(gp.GPError):
+                gp.gp_eval_batch(dd, jobs, gp.BatchConfig(vi, 8, 1, 0))
+            continue
         gp.gp_eval_batch(dd, jobs, gp.BatchConfig(vi, 8, 1, 0))
         torch.cuda.synchronize()
         assert fitness_close(out_t.cpu().numpy(), ref_t).all()

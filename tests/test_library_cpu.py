@@ -76,7 +76,7 @@ def run_lowered(words, X):
             elif op == 1: R = A - B
             elif op == 2: R = A * B
             elif op == 3: R = np.where(np.abs(B) < np.float32(1e-6), np.float32(1), A / B)
-            elif op == 8: R = A
+            elif op == 15: R = A          # push
             else: raise AssertionError("op")
         st.append(R.astype(np.float32))
         assert len(st) == hafter
