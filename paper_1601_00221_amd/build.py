@@ -62,11 +62,11 @@ def _check_reserved(stderr: str, variant) -> None:
     compiler's inline-asm warnings: every VGPR the core clobbers must be
     reported as reserved."""
     gen_core = _gen_core()
-    t, d, nf, ncv = variant[:4]
+    t, d, nf, ncv, mode = variant
     reserved = set()
     for m in re.finditer(r"clobber list contains reserved registers: ([^\[\n]*)", stderr):
         reserved.update(x.strip() for x in m.group(1).split(","))
-    end = ncv + max(gen_core.LIN_REGS, d) * t + nf * t
+    end = ncv + gen_core.reg_levels(d, mode) * t + nf * t
     missing = [n for n in range(ncv, end) if "v%d" % n not in reserved]
     if missing:
         raise RuntimeError("the compiler may allocate core VGPRs %s (variant %s)" % (missing[:8], variant))

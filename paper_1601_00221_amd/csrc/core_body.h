@@ -106,7 +106,8 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
                                              int32_t n_load, int32_t kind, uint64_t pbase, uint32_t tile,
                                              uint32_t q0, uint32_t q1, const double* tab) {
     static_assert(T % 4 == 0, "a tile holds whole 256-case blocks");
-    constexpr int RB = D > GPX_LIN_REGS ? D : GPX_LIN_REGS;   // register/stack levels before the features
+    // register/stack levels before the features (Boolean kernels: trees only)
+    constexpr int RB = (MODE == 2 || D > GPX_LIN_REGS) ? D : GPX_LIN_REGS;
     const uint32_t lane = threadIdx.x & 63u;
     const int64_t tile0 = (int64_t)tile * (64 * T);            // first case of the tile (uniform)
     const int64_t left = N - tile0;                            // cases from the tile start to the end

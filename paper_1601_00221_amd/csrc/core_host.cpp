@@ -39,7 +39,11 @@ uint32_t key_of(int kind, int op, int p1, int p2) {
 
 const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
 int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
-int core_reg_levels(int vi) { return kCoreVariants[vi].d > GPX_LIN_REGS ? kCoreVariants[vi].d : GPX_LIN_REGS; }
+int core_reg_levels(int vi) {
+    // Boolean kernels run trees only: no linear registers before the features
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    return v.arith == 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
+}
 
 int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean) {
     // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
@@ -50,7 +54,7 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
     const bool heavy = transc_frac > 0.2;
     int best = -1;
     auto waves = [](const CoreVariantDesc& v) {
-        const int lv = v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
+        const int lv = v.arith == 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
         const int vg = (v.ncv + lv * v.t + v.nf * v.t + 7) / 8 * 8;
         return 512 / vg;
     };
@@ -59,7 +63,8 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
         return v.arith * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
     };
     // Boolean programs: the most slots in flight per SIMD (waves x tile width)
-    auto score_bool = [&](const CoreVariantDesc& v) { return waves(v) * v.t * 1000 - v.nf; };
+    // (ties: more VGPRs for the compiled code, then fewer feature slots)
+    auto score_bool = [&](const CoreVariantDesc& v) { return waves(v) * v.t * 100000 + v.ncv * 100 - v.nf; };
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
         if ((v.arith == 2) != boolean) continue;

@@ -14,7 +14,8 @@ that range, relative to its first register V0:
     stack level l / linear register r, slot j :  l*T + j        (l < RB)
     feature f, slot j                          :  RB*T + f*T + j  (f < NF)
 
-with RB = max(8, D) register/stack levels.
+with RB = max(8, D) register/stack levels (RB = D in the Boolean kernels,
+which run trees only).
 
 A program is a list of 16-byte instructions
 
@@ -68,6 +69,7 @@ VARIANTS = [
     (8, 8, 8, 40, 1),
     (4, 8, 16, 40, 1),
     (4, 12, 32, 40, 1),
+    (8, 6, 20, 48, 2),
     (8, 8, 20, 32, 2),
     (4, 12, 32, 40, 2),
 ]
@@ -80,11 +82,26 @@ def vname(v):
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
 OP_ID = {"add": 0, "sub": 1, "mul": 2}
-# Boolean functions (ids as the tree opcodes GP_AND .. GP_NOR): one bitwise
-# operation, then a NOT for NAND and NOR
-BOOL_OPS = {"and": ("v_and_b32_e32", False), "or": ("v_or_b32_e32", False),
-            "nand": ("v_and_b32_e32", True), "nor": ("v_or_b32_e32", True)}
+# Boolean functions (ids as the tree opcodes GP_AND .. GP_NOR).  AND and OR
+# are one VOP2 operation; NAND and NOR one v_bitop3_b32, whose truth table
+# has bit (4 s0 + 2 s1 + s2) set where the result is 1 (the third source is
+# ignored by these tables).
+BOOL_OPS = {"and": "v_and_b32_e32", "or": "v_or_b32_e32", "nand": 0x3F, "nor": 0x03}
 BOOL_ID = {"and": 8, "or": 9, "nand": 10, "nor": 11}
+
+
+def bool_op(op, d, a, b):
+    """d = a op b; a and b keep their positions as first and second source."""
+    ins = BOOL_OPS[op]
+    if isinstance(ins, str):
+        return "%s %s, %s, %s" % (ins, d, a, b)
+    return "v_bitop3_b32 %s, %s, %s, %s bitop3:0x%x" % (d, a, b, b, ins)
+
+
+def reg_levels(D, mode):
+    """Register/stack levels before the features: linear programs need
+    LIN_REGS registers; Boolean kernels run trees only."""
+    return D if mode == 2 else max(LIN_REGS, D)
 
 # handler kinds (keep in sync with the generated enum below)
 KINDS = ["EXIT", "SS", "SSR", "SX", "XS", "SC", "CS", "XX", "XX2", "XC", "CX", "PUSHX", "PUSHC",
@@ -95,6 +112,12 @@ K = {k: i for i, k in enumerate(KINDS)}
 def vr(n):
     assert 0 <= n < 256, n
     return "v%d" % n
+
+
+def insn_bytes(text):
+    """Encoded size of an instruction the handlers use: scalar loads and VOP3
+    (v_bitop3_b32) take 8 bytes, everything else 4."""
+    return 8 if text.startswith(("s_load", "v_bitop3")) else 4
 
 
 class Handler:
@@ -110,7 +133,7 @@ class Handler:
 
 def gen_variant(T, D, NF, NCV, mode=0):
     V0 = NCV
-    FO = max(LIN_REGS, D) * T          # register/stack block, then the features
+    FO = reg_levels(D, mode) * T       # register/stack block, then the features
     assert FO + NF * T <= 256, "index range exceeds 8 bits"
     assert V0 + FO + NF * T <= 256
     assert NCV % 8 == 0
@@ -143,7 +166,7 @@ def gen_variant(T, D, NF, NCV, mode=0):
         h.emit("s_setpc_b64 s[64:65]", 4)
 
     def valu(h, text):
-        h.emit(text, 4)
+        h.emit(text, insn_bytes(text))
 
     # ---------------------------------------------------------------- exit
     h = Handler(K["EXIT"])
@@ -322,32 +345,26 @@ def gen_variant(T, D, NF, NCV, mode=0):
 def bool_handlers(hs, T, D, V0, FO, prologue, idx_on, epilogue, valu):
     """Handlers of the Boolean function set.  Every function is symmetric, so
     only the forms with the stack (or first) operand on the left exist: SS,
-    SX, XX2 (two features, two passes) and PUSHX.  NAND and NOR complement
-    the result with v_not_b32, whose source is never an indexed operand."""
-    for op, (ins, neg) in BOOL_OPS.items():
+    SX, XX2 (two features, two passes) and PUSHX.  Each function is one
+    vector instruction per slot; the index mode offsets the same sources and
+    destination in every encoding."""
+    for op in BOOL_OPS:
         h = Handler(K["SS"], BOOL_ID[op])           # s[h-2] = s[h-2] op s[h-1]; index (h-2)*T
         prologue(h, index=["SRC0", "SRC1", "DST"])
         for j in range(T):
-            valu(h, "%s %s, %s, %s" % (ins, vr(V0 + j), vr(V0 + j), vr(V0 + T + j)))
-        if neg:                                     # source and destination share the index
-            for j in range(T):
-                valu(h, "v_not_b32_e32 %s, %s" % (vr(V0 + j), vr(V0 + j)))
+            valu(h, bool_op(op, vr(V0 + j), vr(V0 + j), vr(V0 + T + j)))
         epilogue(h)
         hs.append(h)
-    for op, (ins, neg) in BOOL_OPS.items():
+    for op in BOOL_OPS:
         for l in range(D):
             h = Handler(K["SX"], BOOL_ID[op], l)    # s[l] = s[l] op x[b]; index = feature offset
             prologue(h, index=["SRC1"])
             for j in range(T):
                 r = vr(V0 + l * T + j)
-                valu(h, "%s %s, %s, %s" % (ins, r, r, vr(V0 + j)))
-            if neg:                                 # only SRC1 is indexed
-                for j in range(T):
-                    r = vr(V0 + l * T + j)
-                    valu(h, "v_not_b32_e32 %s, %s" % (r, r))
+                valu(h, bool_op(op, r, r, vr(V0 + j)))
             epilogue(h)
             hs.append(h)
-    for op, (ins, neg) in BOOL_OPS.items():
+    for op in BOOL_OPS:
         for l in range(D):
             h = Handler(K["XX2"], BOOL_ID[op], l)   # s[l] = x[b]; s[l] = x[a] op s[l]
             prologue(h, second_index=True)
@@ -357,12 +374,7 @@ def bool_handlers(hs, T, D, V0, FO, prologue, idx_on, epilogue, valu):
             idx_on(h, "s70", ["SRC0"])
             for j in range(T):
                 r = vr(V0 + l * T + j)
-                valu(h, "%s %s, %s, %s" % (ins, r, vr(V0 + j), r))
-            if neg:                                 # the NOT reads s[l] itself: index off
-                h.emit("s_set_gpr_idx_off", 4)
-                for j in range(T):
-                    r = vr(V0 + l * T + j)
-                    valu(h, "v_not_b32_e32 %s, %s" % (r, r))
+                valu(h, bool_op(op, r, vr(V0 + j), r))
             epilogue(h)
             hs.append(h)
     h = Handler(K["PUSHX"])                         # s[0] = x[a] (a program that is one variable)
@@ -418,7 +430,7 @@ def phase_a(h, tag):
         x = x.replace("s72", "s67")
         body.append(x)
     for x in body:
-        c.emit(x, 8 if x.startswith("s_load") else 4)
+        c.emit(x, insn_bytes(x))
     c.emit("s_add_u32 s62, s62, 16", 4)
     c.emit("s_setpc_b64 s[68:69]", 4)
     return c
@@ -447,7 +459,7 @@ def phase_b(h, tag):
             x = x.replace("s_set_gpr_idx_on s70,", "s_set_gpr_idx_on s73,")
         elif x.startswith("s_set_gpr_idx_on s71,"):
             x = x.replace("s_set_gpr_idx_on s71,", "s_set_gpr_idx_on s74,")
-        c.emit(x, 8 if x.startswith("s_load") else 4)
+        c.emit(x, insn_bytes(x))
     return c
 
 

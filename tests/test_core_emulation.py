@@ -74,6 +74,9 @@ class CoreEmu:
         if op == "s_branch":
             assert ".Lgpx_end_" in rest
             return (op,)
+        if op == "v_bitop3_b32":
+            regs, table = rest.split(" bitop3:")
+            return (op, [self._reg(a) for a in regs.split(",")] + [("t", int(table, 0))])
         args = [self._reg(a) for a in rest.split(",")]
         return (op, args)
 
@@ -138,6 +141,17 @@ class CoreEmu:
         assert self.V0 <= dr < 256, dr
         if op == "v_mov_b32_e32":
             self.v[dr] = src(*args[1], "SRC0")
+            return
+        if op == "v_bitop3_b32":
+            # bit i of the table is the result for sources (s0, s1, s2) = bits of i, s0 the highest
+            A = src(*args[1], "SRC0").view(np.uint32)
+            B = src(*args[2], "SRC1").view(np.uint32)
+            Cc = src(*args[3], "SRC2").view(np.uint32)
+            r = np.zeros(64, np.uint32)
+            for i in range(8):
+                if (args[4][1] >> i) & 1:
+                    r |= (A if i & 4 else ~A) & (B if i & 2 else ~B) & (Cc if i & 1 else ~Cc)
+            self.v[dr] = r.view(np.float32)
             return
         if op == "v_not_b32_e32":
             self.v[dr] = (~src(*args[1], "SRC0").view(np.uint32)).view(np.float32)
