@@ -156,6 +156,65 @@ gp_status gp_eval_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, c
                        void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* GP runs around the evaluator.  The paper measures GPop/s over whole GP   */
+/* runs with the parameters of Table 2; these calls breed tree populations  */
+/* on the host (Koza-style tree GP) and evaluate every generation with      */
+/* gp_eval_tree, or gp_eval_bool for the Boolean function set.              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t pop_size;          /* Table 2: 1000 */
+    int32_t generations;       /* generations bred after the initial one; Table 2: 50 */
+    int32_t max_depth;         /* edges from the root; Table 2: 50 */
+    int32_t max_size;          /* nodes; Table 2: 1000 */
+    int32_t tournament;        /* Table 2: 7 */
+    float p_crossover;         /* Table 2: 0.95 */
+    float p_mutation;          /* Table 2: 0.2 */
+    int32_t init_min_depth;    /* ramped half-and-half range, e.g. 2 .. 6 */
+    int32_t init_max_depth;
+    int32_t mutation_depth;    /* depth limit of a mutation's new subtree, e.g. 4 */
+    uint32_t functions;        /* bit k set: opcode k (GP_ADD .. GP_NOR) is in the function set; all
+                                  arithmetic or all Boolean */
+    float p_const;             /* probability that a terminal is a constant (arithmetic sets) */
+    float const_lo, const_hi;  /* constants uniform in [const_lo, const_hi) */
+    int32_t kind;              /* GP_FIT_MSE or GP_FIT_SUM_ABS (minimised) or GP_FIT_HITS (maximised;
+                                  the only kind for Boolean sets) */
+    uint64_t seed;             /* SplitMix64 seed: a run is reproducible from it */
+} gp_evolve_config;
+
+typedef struct {
+    double best_fitness;       /* of the best program seen: its error, or its hit count */
+    int32_t best_generation;
+    int32_t best_size;         /* nodes */
+    int32_t generations_run;   /* evaluated generations, the initial one included */
+    int32_t pad;
+    int64_t gp_ops;            /* sum over evaluations of tree nodes x cases */
+    double eval_seconds;       /* host lowering, upload, kernels and fitness copy-back */
+    double breed_seconds;      /* selection, crossover and mutation on the host */
+    double total_seconds;      /* the whole run */
+} gp_evolve_result;
+
+/* One GP run on a case matrix: X, y as for gp_eval_tree (arithmetic sets) or
+ * gp_eval_bool (Boolean sets, n_cases in bits).  best_per_gen (HOST, may be
+ * NULL) receives the best fitness so far after each generation
+ * (generations + 1 values); best_tok/best_cst (HOST, may be NULL) receive
+ * the best program if best_cap >= its size.  Synchronous on `stream`. */
+gp_status gp_evolve(const gp_evolve_config* cfg, const void* X, int32_t n_feat, int64_t n_cases, const void* y,
+                    double* best_per_gen, int32_t* best_tok, float* best_cst, int32_t best_cap,
+                    gp_evolve_result* res, void* stream);
+/* The run's host steps on their own (no device needed), for inspection and
+ * tests.  gp_init_population writes cfg->pop_size ramped half-and-half trees
+ * in CSR form (off has pop_size + 1 entries).  gp_breed takes a population
+ * of cfg->pop_size trees (cst may be NULL for Boolean sets) and each
+ * program's score (lower is better; NaN is worst) and writes the next
+ * generation, with random numbers from `seed`.  GP_E_NOMEM if the result
+ * exceeds max_tokens. */
+gp_status gp_init_population(const gp_evolve_config* cfg, int32_t n_feat, int32_t* tok, float* cst, int64_t* off,
+                             int64_t max_tokens);
+gp_status gp_breed(const gp_evolve_config* cfg, const int32_t* tok, const float* cst, const int64_t* off,
+                   int32_t n_feat, const double* score, uint64_t seed, int32_t* out_tok, float* out_cst,
+                   int64_t* out_off, int64_t max_tokens);
+
+/* ------------------------------------------------------------------------ */
 /* Resident program sets: lower and upload once, evaluate many times        */
 /* (a GP generation evaluated on several datasets, or timed repeatedly).    */
 /* ------------------------------------------------------------------------ */

@@ -37,6 +37,74 @@ class LowerStats(C.Structure):
                 ("stack_fetches", C.c_int32), ("n_values", C.c_int32), ("n_reversed", C.c_int32)]
 
 
+class EvolveConfig(C.Structure):
+    _fields_ = [("pop_size", C.c_int32), ("generations", C.c_int32), ("max_depth", C.c_int32),
+                ("max_size", C.c_int32), ("tournament", C.c_int32), ("p_crossover", C.c_float),
+                ("p_mutation", C.c_float), ("init_min_depth", C.c_int32), ("init_max_depth", C.c_int32),
+                ("mutation_depth", C.c_int32), ("functions", C.c_uint32), ("p_const", C.c_float),
+                ("const_lo", C.c_float), ("const_hi", C.c_float), ("kind", C.c_int32), ("seed", C.c_uint64)]
+
+
+class EvolveResult(C.Structure):
+    _fields_ = [("best_fitness", C.c_double), ("best_generation", C.c_int32), ("best_size", C.c_int32),
+                ("generations_run", C.c_int32), ("pad", C.c_int32), ("gp_ops", C.c_int64),
+                ("eval_seconds", C.c_double), ("breed_seconds", C.c_double), ("total_seconds", C.c_double)]
+
+
+def evolve_config(functions, kind="mse", pop_size=1000, generations=50, max_depth=50, max_size=1000,
+                  tournament=7, p_crossover=0.95, p_mutation=0.2, init_depth=(2, 6), mutation_depth=4,
+                  p_const=0.0, const_range=(-1.0, 1.0), seed=1):
+    """A gp_evolve_config; the defaults are the paper's Table 2 parameters.
+    functions: opcodes of the function set."""
+    mask = 0
+    for op in functions:
+        mask |= 1 << int(op)
+    return EvolveConfig(pop_size, generations, max_depth, max_size, tournament, p_crossover, p_mutation,
+                        init_depth[0], init_depth[1], mutation_depth, mask, p_const, const_range[0],
+                        const_range[1], kind_id(kind), seed)
+
+
+def _csr_out(cfg):
+    cap = cfg.pop_size * cfg.max_size
+    return np.zeros(cap, np.int32), np.zeros(cap, np.float32), np.zeros(cfg.pop_size + 1, np.int64), cap
+
+
+def init_population(cfg, n_feat):
+    """gp_init_population: (tok, cst, off) of the initial population (host only)."""
+    tok, cst, off, cap = _csr_out(cfg)
+    check(lib().gp_init_population(C.byref(cfg), n_feat, tok.ctypes.data, cst.ctypes.data, off.ctypes.data, cap))
+    return tok[:off[-1]], cst[:off[-1]], off
+
+
+def breed(cfg, tok, cst, off, n_feat, score, seed):
+    """gp_breed: the next generation of a population (host only)."""
+    tok, tp = _np(tok, np.int32)
+    cst, cp = _np(cst, np.float32)
+    off, op = _np(off, np.int64)
+    score, sp = _np(score, np.float64)
+    ot, oc, oo, cap = _csr_out(cfg)
+    check(lib().gp_breed(C.byref(cfg), tp, cp, op, n_feat, sp, seed, ot.ctypes.data, oc.ctypes.data,
+                         oo.ctypes.data, cap))
+    return ot[:oo[-1]], oc[:oo[-1]], oo
+
+
+def evolve(cfg, X, y, n_cases=None, stream=None):
+    """gp_evolve: one GP run; X, y device tensors (float32, or 32-bit words
+    for a Boolean function set with n_cases in bits).  Returns a dict with
+    the result fields, the best fitness per generation and the best program."""
+    n = int(X.shape[1]) if n_cases is None else int(n_cases)
+    per_gen = np.zeros(cfg.generations + 1, np.float64)
+    bt = np.zeros(cfg.max_size, np.int32)
+    bc = np.zeros(cfg.max_size, np.float32)
+    r = EvolveResult()
+    check(lib().gp_evolve(C.byref(cfg), dptr(X), int(X.shape[0]), n, dptr(y), per_gen.ctypes.data,
+                          bt.ctypes.data, bc.ctypes.data, cfg.max_size, C.byref(r), stream_ptr(stream)))
+    out = {k: getattr(r, k) for k, _ in EvolveResult._fields_ if k != "pad"}
+    out["best_per_generation"] = per_gen[:r.generations_run]
+    out["best_tok"], out["best_cst"] = bt[:r.best_size].copy(), bc[:r.best_size].copy()
+    return out
+
+
 class ProgsetInfo(C.Structure):
     _fields_ = [("n_prog", C.c_int32), ("form", C.c_int32), ("n_feat", C.c_int32),
                 ("max_depth", C.c_int32), ("n_instr", C.c_int64), ("n_gpop", C.c_int64),
@@ -58,6 +126,9 @@ def lib():
             "gp_eval_tree": [P, P, P, i32, P, i32, i64, P, i32, P, P],
             "gp_eval_tree_1d": [P, P, P, i32, P, i32, i64, P, i32, i32, P, P],
             "gp_eval_bool": [P, P, i32, P, i32, i64, P, i32, P, P],
+            "gp_evolve": [P, P, i32, i64, P, P, P, P, i32, P, P],
+            "gp_init_population": [P, i32, P, P, P, i64],
+            "gp_breed": [P, P, P, P, i32, P, C.c_uint64, P, P, P, i64],
             "gp_eval_linear": [P, P, P, P, i32, i32, P, i32, i64, P, i32, P, P],
             "gp_progset_tree": [P, P, P, i32, i32, P, P],
             "gp_progset_linear": [P, P, P, P, i32, i32, i32, P, P],
