@@ -307,11 +307,14 @@ gp_status gp_tune_batch(const gp_dataset* ds, int32_t n_ds, const gp_job* jobs, 
  * the VGPRs from that number up) and flags: GP_VARIANT_NO_TRANSC marks a
  * kernel without sin/cos/exp/log code, used for programs without them;
  * GP_VARIANT_BOOLEAN (with GP_VARIANT_NO_TRANSC) a kernel of the Boolean
- * function set for gp_eval_bool, whose slots are 32-bit words.  The
- * variant's kernel is named k_core_<t>_<depth>_<n_feat>_<vgprs>, with "_a"
- * appended for an arithmetic-only and "_b" for a Boolean kernel.  Any
+ * function set for gp_eval_bool, whose slots are 32-bit words;
+ * GP_VARIANT_TREES_ONLY (with GP_VARIANT_NO_TRANSC) an arithmetic kernel for
+ * trees only (no linear-program handlers), which one-shot and program-set
+ * evaluations of trees prefer and batches do not use.  The variant's kernel
+ * is named k_core_<t>_<depth>_<n_feat>_<vgprs>, with "_a" appended for an
+ * arithmetic-only, "_at" for a trees-only and "_b" for a Boolean kernel.  Any
  * pointer may be NULL. */
-enum { GP_VARIANT_NO_TRANSC = 1, GP_VARIANT_BOOLEAN = 2 };
+enum { GP_VARIANT_NO_TRANSC = 1, GP_VARIANT_BOOLEAN = 2, GP_VARIANT_TREES_ONLY = 4 };
 int32_t gp_num_variants(void);
 gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat, int32_t* vgprs, int32_t* flags);
 

@@ -446,10 +446,10 @@ def variants():
     for i in range(L.gp_num_variants()):
         t, d, f, v, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f), C.byref(v), C.byref(fl)))
-        arith, boolean = bool(fl.value & 1), bool(fl.value & 2)
-        suffix = "_b" if boolean else ("_a" if arith else "")
+        arith, boolean, trees = bool(fl.value & 1), bool(fl.value & 2), bool(fl.value & 4)
+        suffix = "_b" if boolean else ("_at" if trees else ("_a" if arith else ""))
         out.append({"t": t.value, "depth": d.value, "n_feat": f.value, "vgprs": v.value, "no_transc": arith,
-                    "boolean": boolean,
+                    "boolean": boolean, "trees_only": trees,
                     "kernel": "k_core_%d_%d_%d_%d%s" % (t.value, d.value, f.value, v.value, suffix)})
     return out
 

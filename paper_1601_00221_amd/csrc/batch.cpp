@@ -62,6 +62,9 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
     if (core_variant_arith(vi) && any_transc)
         return fail(GP_E_INVAL, "variant %d has no sin/cos/exp/log code", vi);
     if (core_variant_bool(vi)) return fail(GP_E_INVAL, "variant %d is a Boolean kernel", vi);
+    if (core_variant_trees_only(vi))
+        for (const BatchJobRef& j : jobs)
+            if (j.pd->form != FORM_TREE) return fail(GP_E_INVAL, "variant %d runs trees only", vi);
     plan.vi = vi;
     const int32_t unit_prog = std::max(1, cfg.unit_programs);
     int64_t n_prog = 0;
@@ -343,7 +346,7 @@ gp_status tune_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
     for (int vi = 0; vi < core_variants(); vi++) {
         if (core_variant_nf(vi) < n_load || core_variant_d(vi) < depth) continue;
         if (core_variant_arith(vi) && any_transc) continue;
-        if (core_variant_bool(vi)) continue;
+        if (core_variant_bool(vi) || core_variant_trees_only(vi)) continue;
         for (int us : unit_sizes) {
             for (int pers = 1; pers >= 0; pers--) {
                 gp_batch_config c;
@@ -520,7 +523,9 @@ gp_status gp_variant_info(int32_t i, int32_t* t, int32_t* depth, int32_t* n_feat
     if (depth) *depth = core_variant_d(i);
     if (n_feat) *n_feat = core_variant_nf(i);
     if (vgprs) *vgprs = core_variant_ncv(i);
-    if (flags) *flags = (core_variant_arith(i) ? GP_VARIANT_NO_TRANSC : 0) | (core_variant_bool(i) ? GP_VARIANT_BOOLEAN : 0);
+    if (flags)
+        *flags = (core_variant_arith(i) ? GP_VARIANT_NO_TRANSC : 0) | (core_variant_bool(i) ? GP_VARIANT_BOOLEAN : 0) |
+                 (core_variant_trees_only(i) && !core_variant_bool(i) ? GP_VARIANT_TREES_ONLY : 0);
     return GP_OK;
 }
 

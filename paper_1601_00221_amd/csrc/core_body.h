@@ -22,7 +22,7 @@
 // shared the launch.
 //
 // Kernel modes: 0 with the sin/cos/exp/log code, 1 without it (arithmetic
-// programs), 2 the Boolean function set, whose slots are 32-bit words of
+// programs), 3 like 1 for trees only, 2 the Boolean function set, whose slots are 32-bit words of
 // bit-packed cases (32 cases per slot; a 256-slot block holds 8192 cases)
 // and whose fitness is the number of output bits equal to the target bits.
 #pragma once
@@ -106,8 +106,8 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
                                              int32_t n_load, int32_t kind, uint64_t pbase, uint32_t tile,
                                              uint32_t q0, uint32_t q1, const double* tab) {
     static_assert(T % 4 == 0, "a tile holds whole 256-case blocks");
-    // register/stack levels before the features (Boolean kernels: trees only)
-    constexpr int RB = (MODE == 2 || D > GPX_LIN_REGS) ? D : GPX_LIN_REGS;
+    // register/stack levels before the features (Boolean and trees-only kernels: no linear registers)
+    constexpr int RB = (MODE >= 2 || D > GPX_LIN_REGS) ? D : GPX_LIN_REGS;
     const uint32_t lane = threadIdx.x & 63u;
     const int64_t tile0 = (int64_t)tile * (64 * T);            // first case of the tile (uniform)
     const int64_t left = N - tile0;                            // cases from the tile start to the end
@@ -142,7 +142,7 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             uint64_t table;
             uint32_t probe = a.probe;
             asm volatile("" : "+s"(probe));
-            Core<T, D, NF, V0, MODE == 2>::run(code, off, pay, cst, probe, pf_end, table);
+            Core<T, D, NF, V0, (MODE >= 2 ? MODE : 0)>::run(code, off, pay, cst, probe, pf_end, table);
             // later passes skip the prefetch; an opaque 0, so the first pass is not peeled off
             pf_end = 0u;
             asm volatile("" : "+s"(pf_end));

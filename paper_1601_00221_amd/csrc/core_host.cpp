@@ -42,10 +42,10 @@ int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[
 int core_reg_levels(int vi) {
     // Boolean kernels run trees only: no linear registers before the features
     const CoreVariantDesc& v = kCoreVariants[vi];
-    return v.arith == 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
+    return v.arith >= 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
 }
 
-int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean) {
+int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean, bool trees_only) {
     // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
     // outside the core) run best with room for that code (no spills) and as
     // many waves per SIMD as that leaves, to hide its latency; the others with
@@ -54,13 +54,15 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
     const bool heavy = transc_frac > 0.2;
     int best = -1;
     auto waves = [](const CoreVariantDesc& v) {
-        const int lv = v.arith == 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
+        const int lv = v.arith >= 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
         const int vg = (v.ncv + lv * v.t + v.nf * v.t + 7) / 8 * 8;
         return 512 / vg;
     };
     auto score = [&](const CoreVariantDesc& v) {
         if (heavy) return (v.ncv >= 64) * 100000000 + waves(v) * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
-        return v.arith * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
+        // trees-only kernels first (the smallest handler tables), then those without sin/cos/exp/log code
+        return (v.arith == 3) * 400000000 + (v.arith != 0) * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 -
+               v.nf * 100 - v.n / 100;
     };
     // Boolean programs: the most slots in flight per SIMD (waves x tile width)
     // (ties: more VGPRs for the compiled code, then fewer feature slots)
@@ -68,6 +70,7 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
         if ((v.arith == 2) != boolean) continue;
+        if (v.arith == 3 && !trees_only) continue;
         if (v.nf < n_load || v.d < depth || (v.arith && has_transc)) continue;
         if (best < 0) { best = i; continue; }
         const bool better = boolean ? score_bool(v) > score_bool(kCoreVariants[best])
@@ -198,7 +201,7 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
                     else e.put(CK_CS, op, 0, 0, (uint32_t)((h - 1) * T), c);
                     break;
                 case M_XX:
-                    if (v.nf <= 8 && v.arith != 2) {
+                    if (v.nf <= 8 && v.arith != 2) {   // (Boolean kernels have no one-pass XX handlers)
                         if (comm) {
                             const int a = fa < fb ? fa : fb, b = fa < fb ? fb : fa;
                             e.put(CK_XX, op, h, b - a, (uint32_t)(a * T), 0);
@@ -347,5 +350,6 @@ int core_variant_d(int vi) { return kCoreVariants[vi].d; }
 int core_variant_nf(int vi) { return kCoreVariants[vi].nf; }
 int core_variant_arith(int vi) { return kCoreVariants[vi].arith != 0; }
 bool core_variant_bool(int vi) { return kCoreVariants[vi].arith == 2; }
+bool core_variant_trees_only(int vi) { return kCoreVariants[vi].arith >= 2; }
 
 }  // namespace gpx

@@ -18,12 +18,16 @@ int core_variant_d(int vi);        // stack levels
 int core_variant_nf(int vi);       // feature slots
 int core_variant_arith(int vi);    // 1: no sin/cos/exp/log code
 bool core_variant_bool(int vi);    // the Boolean function set (32-bit word slots)
+bool core_variant_trees_only(int vi);   // no linear handlers (Boolean and trees-only arithmetic kernels)
 int core_variant_ncv(int vi);      // VGPRs left to the compiled code
 int core_reg_levels(int vi);       // register/stack levels before the features
 // Variant for programs reading n_load features, needing `depth` stack levels,
 // with a fraction transc_frac of sin/cos/exp/log instructions (has_transc:
-// any at all), of the Boolean function set if `boolean`; -1 if none fits.
-int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean = false);
+// any at all), of the Boolean function set if `boolean`, and trees only if
+// `trees_only` (then a kernel without linear handlers may be taken); -1 if
+// none fits.
+int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean = false,
+                      bool trees_only = false);
 // Locate the variant's handler table on the current device (one probe launch
 // on stream s the first time).
 gp_status core_ready(int vi, hipStream_t s);

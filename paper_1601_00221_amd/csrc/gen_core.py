@@ -49,7 +49,9 @@ LIN_REGS = 8              # register slots reserved for linear programs (and sta
 # MODE = 0 for the arithmetic function set with the sin/cos/exp/log code,
 # 1 without that code (for programs that use none; its compiled part is
 # small, so nothing spills), 2 for the Boolean function set (slots are
-# 32-bit words of bit-packed cases).  Work that leaves the core (sin/cos/
+# 32-bit words of bit-packed cases), 3 like 1 for trees only (no linear
+# handlers or registers: a handler table half the size, and the stack
+# levels start the VGPR range).  Work that leaves the core (sin/cos/
 # exp/log in binary64, protected division) runs in the compiler's VGPRs:
 # programs rich in it take a variant with room for it.
 VARIANTS = [
@@ -69,6 +71,8 @@ VARIANTS = [
     (8, 8, 8, 40, 1),
     (4, 8, 16, 40, 1),
     (4, 12, 32, 40, 1),
+    (8, 6, 8, 56, 3),
+    (8, 8, 8, 40, 3),
     (8, 6, 20, 48, 2),
     (8, 8, 20, 32, 2),
     (4, 12, 32, 40, 2),
@@ -77,8 +81,9 @@ VARIANTS = [
 
 def vname(v):
     """Kernel name suffix of a variant: T_D_NF_NCV, plus _a when it has no
-    sin/cos/exp/log code and _b for the Boolean function set."""
-    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], ("", "_a", "_b")[v[4]])
+    sin/cos/exp/log code, _at when it also runs trees only, and _b for the
+    Boolean function set."""
+    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], ("", "_a", "_b", "_at")[v[4]])
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
 OP_ID = {"add": 0, "sub": 1, "mul": 2}
@@ -100,8 +105,8 @@ def bool_op(op, d, a, b):
 
 def reg_levels(D, mode):
     """Register/stack levels before the features: linear programs need
-    LIN_REGS registers; Boolean kernels run trees only."""
-    return D if mode == 2 else max(LIN_REGS, D)
+    LIN_REGS registers; Boolean and trees-only kernels have none."""
+    return D if mode >= 2 else max(LIN_REGS, D)
 
 # handler kinds (keep in sync with the generated enum below)
 KINDS = ["EXIT", "SS", "SSR", "SX", "XS", "SC", "CS", "XX", "XX2", "XC", "CX", "PUSHX", "PUSHC",
@@ -137,7 +142,7 @@ def gen_variant(T, D, NF, NCV, mode=0):
     assert FO + NF * T <= 256, "index range exceeds 8 bits"
     assert V0 + FO + NF * T <= 256
     assert NCV % 8 == 0
-    tag = "T%dD%dF%dV%d%s" % (T, D, NF, NCV, "B" if mode == 2 else "")
+    tag = "T%dD%dF%dV%d%s" % (T, D, NF, NCV, {2: "B", 3: "R"}.get(mode, ""))
     hs = []
 
     def prologue(h, const=False, second_index=False, index=None):
@@ -276,6 +281,9 @@ def gen_variant(T, D, NF, NCV, mode=0):
         valu(h, "v_mov_b32_e32 %s, s72" % vr(V0 + j))
     epilogue(h)
     hs.append(h)
+
+    if mode == 3:                      # trees only: no linear handlers
+        return finish(hs, tag, V0, FO)
 
     # ---------------------------------------------------------------- linear
     R = LIN_REGS
@@ -547,7 +555,7 @@ def main(out_dir):
     lines.append(" \\\n".join("    X(%d, %d, %d, %d, %d)" % v for v in VARIANTS))
     lines.append("")
     clob_s = ", ".join('"s%d"' % n for n in (63, 64, 65, 66, 67, 70, 71, 72, 76, 77))
-    lines.append("template <int T, int D, int NF, int V0, bool B> struct Core;")
+    lines.append("template <int T, int D, int NF, int V0, int K> struct Core;   // K: 0 arithmetic, 2 Boolean, 3 trees only")
     lines.append("template <int T, int V0> __device__ void core_gather(uint32_t off, float (&v)[T]);")
     lines.append("template <int T, int V0> __device__ void core_scatter(uint32_t off, const float (&v)[T]);")
     for T, V0 in sorted(set((v[0], v[3]) for v in VARIANTS)):
@@ -556,15 +564,16 @@ def main(out_dir):
     seen = {}
     for (T, D, NF, NCV, AR) in VARIANTS:
         B = AR == 2
-        if (T, D, NF, NCV, B) in seen:    # same core as another variant
-            host.append((T, D, NF, NCV, AR) + seen[(T, D, NF, NCV, B)])
+        core = (T, D, NF, NCV, AR if AR >= 2 else 0)   # modes 0 and 1 share a core
+        if core in seen:
+            host.append((T, D, NF, NCV, AR) + seen[core])
             continue
         tag, V0, FO, hs, nslots = gen_variant(T, D, NF, NCV, AR)
-        seen[(T, D, NF, NCV, B)] = (tag, hs, nslots)
+        seen[core] = (tag, hs, nslots)
         text = asm_text(T, D, NF, tag, hs)
         clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
         assert NCV + FO + NF * T <= 256
-        lines.append("template <> struct Core<%d, %d, %d, %d, %s> {" % (T, D, NF, NCV, "true" if B else "false"))
+        lines.append("template <> struct Core<%d, %d, %d, %d, %d> {" % (T, D, NF, NCV, core[4]))
         lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")
         lines.append("    // pf_end: byte offset where the program ends (its code is first burst-loaded into the")
         lines.append("    // scalar cache), or 0")

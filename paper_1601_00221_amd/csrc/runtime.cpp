@@ -415,11 +415,12 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     const int vi = opt && opt->variant >= 0
                        ? opt->variant
                        : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0,
-                                           pd.n_transc > 0, boolean);
+                                           pd.n_transc > 0, boolean, pd.form == FORM_TREE);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth ||
-        (core_variant_arith(vi) && pd.n_transc > 0) || core_variant_bool(vi) != boolean)
+        (core_variant_arith(vi) && pd.n_transc > 0) || core_variant_bool(vi) != boolean ||
+        (core_variant_trees_only(vi) && pd.form != FORM_TREE))
         return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
     gp_status st;
     if ((st = core_ready(vi, s)) != GP_OK) return st;
@@ -616,7 +617,7 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->n_gpop = ps->pd.n_gpop;
     info->variant = pick_core_variant(ps->pd.n_load, ps->pd.max_depth,
                                       ps->pd.n_instr ? (double)ps->pd.n_transc / ps->pd.n_instr : 0.0,
-                                      ps->pd.n_transc > 0, ps->pd.opset == OPSET_BOOL);
+                                      ps->pd.n_transc > 0, ps->pd.opset == OPSET_BOOL, ps->pd.form == FORM_TREE);
     info->pad = 0;
     return GP_OK;
 }

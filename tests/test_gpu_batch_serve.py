@@ -217,8 +217,8 @@ def test_every_variant_on_arithmetic_programs():
         out_t = gp.out_tensor("mse", trees.n_prog, 0)
         out_l = gp.out_tensor("mse", lin.n_prog, 0)
         jobs = [gp.make_job(trees, 0, "mse", out_t), gp.make_job(lin, 0, "mse", out_l)]
-        if v["boolean"]:
-            # Boolean kernels take only Boolean trees, and never batched
+        if v["boolean"] or v["trees_only"]:
+            # Boolean kernels take only Boolean trees, trees-only kernels no linear programs
             with pytest.raises(gp.GPError):
                 gp.gp_eval_batch(dd, jobs, gp.BatchConfig(vi, 8, 1, 0))
             continue
