@@ -429,8 +429,9 @@ gp_status gp_timing_read(int64_t* launches, double* total_ms, int reset);
  * instructions per program group), GP2D_TILES_PER_WAVE (case tiles each
  * wavefront walks per group), GP2D_TARGET_BLOCKS (workgroups the launch aims
  * for), GP2D_CODE_PREFETCH=0 (no burst load of each program's code into the
- * scalar cache).  They change the schedule only; fitness values never depend
- * on them. */
+ * scalar cache), GP2D_SAME_GROUP=1 (the four waves of a block run one program
+ * group on four chunks of tiles instead of four groups on one chunk).  They
+ * change the schedule only; fitness values never depend on them. */
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* gp_last_error(void);
