@@ -333,8 +333,11 @@ def test_launch_shapes_give_identical_results(form, monkeypatch):
     kind = "mse"
     ref = None
     # (core instructions per group, tiles per wave, blocks the launch aims for)
-    for gi, tpw, tb in ((0, 0, 0), (1, 1, 1), (7, 3, 1), (40, 2, 1), (100000, 16, 1), (100000, 1, 1),
-                        (192, 5, 1), (192, 0, 4096)):
+    for gi, tpw, tb, sg in ((0, 0, 0, 0), (1, 1, 1, 0), (7, 3, 1, 0), (40, 2, 1, 0), (100000, 16, 1, 0),
+                            (100000, 1, 1, 0), (192, 5, 1, 0), (192, 0, 4096, 0), (7, 3, 1, 1), (192, 0, 4096, 1),
+                            (1, 1, 1, 1)):
+        # sg: the four waves of a block run one group on four chunks of tiles
+        monkeypatch.setenv("GP2D_SAME_GROUP", str(sg))
         if gi:
             monkeypatch.setenv("GP2D_GROUP_INSTR", str(gi))
             monkeypatch.setenv("GP2D_TARGET_BLOCKS", str(tb))
@@ -342,7 +345,7 @@ def test_launch_shapes_give_identical_results(form, monkeypatch):
                 monkeypatch.setenv("GP2D_TILES_PER_WAVE", str(tpw))
             else:
                 monkeypatch.delenv("GP2D_TILES_PER_WAVE", raising=False)
-        say("launch shape %s group_instr=%d tiles_per_wave=%d target_blocks=%d" % (form, gi, tpw, tb))
+        say("launch shape %s group_instr=%d tiles_per_wave=%d target_blocks=%d same_group=%d" % (form, gi, tpw, tb, sg))
         got = gpu_tree(pop, X, y, kind) if form == "tree" else gpu_linear(pop, X, y, kind)
         cases = gpu_tree(pop, X, None, "cases") if form == "tree" else gpu_linear(pop, X, None, "cases")
         if ref is None:
