@@ -428,8 +428,9 @@ gp_status gp_timing_read(int64_t* launches, double* total_ms, int reset);
  * every one-shot or program-set evaluation: GP2D_GROUP_INSTR (core
  * instructions per program group), GP2D_TILES_PER_WAVE (case tiles each
  * wavefront walks per group), GP2D_TARGET_BLOCKS (workgroups the launch aims
- * for), GP2D_CODE_PREFETCH=0 (no burst load of each program's code into the
- * scalar cache), GP2D_SAME_GROUP=1 (the four waves of a block run one program
+ * for), GP2D_CODE_PREFETCH=n (scalar loads in flight, 1-15, when each
+ * program's code is burst-loaded into the scalar cache; 15 by default, 0
+ * for no burst load), GP2D_SAME_GROUP=1 (the four waves of a block run one program
  * group on four chunks of tiles instead of four groups on one chunk).  They
  * change the schedule only; fitness values never depend on them. */
 

@@ -142,7 +142,8 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             uint64_t table;
             uint32_t probe = a.probe;
             asm volatile("" : "+s"(probe));
-            Core<T, D, NF, V0, (MODE >= 2 ? MODE : 0)>::run(code, off, pay, cst, probe, pf_end, table);
+            Core<T, D, NF, V0, (MODE >= 2 ? MODE : 0)>::run(code, off, pay, cst, probe, pf_end,
+                                                            (uint32_t)a.prefetch, table);
             // later passes skip the prefetch; an opaque 0, so the first pass is not peeled off
             pf_end = 0u;
             asm volatile("" : "+s"(pf_end));

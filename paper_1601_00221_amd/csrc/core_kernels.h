@@ -65,7 +65,8 @@ struct CoreArgs {
     int32_t persistent;
     int32_t tiles_per_wave;
     int32_t chunks;
-    int32_t prefetch;           // burst-load each program's code into the scalar cache first
+    int32_t prefetch;           // scalar loads in flight when a program's code is burst-loaded into the
+                                // scalar cache before it runs (1-15), or 0: no burst load
     int32_t n_groups;           // program groups (implicit units)
     int32_t same_group;         // implicit units: the four waves of a block run one group on four chunks
     int64_t n_bits;             // Boolean kernels: cases (bits) in the N words of each row

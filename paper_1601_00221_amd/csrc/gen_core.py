@@ -35,8 +35,10 @@ of a program) leaves the asm block through the exit handler with the
 instruction's payload; the compiled kernel does it and re-enters.
 
 Fixed SGPRs used by the block: s[60:61] code base, s62 byte offset of the
-current instruction, s63 probe flag, s[64:67] current instruction, s70-s71
-indices, s72 constant, s[76:77] table address (probe).
+current instruction, s63 probe flag, s[64:71] the current and next
+instruction records, s72-s74 a constant copy and index temporaries, s75 the
+end of the program's code and s78 the loads in flight for its burst load
+into the scalar cache, s[76:77] table address (probe).
 """
 import os
 import sys
@@ -482,7 +484,7 @@ def asm_text(T, D, NF, tag, hs):
     L.append("s_branch .Lgpx_end_%s" % tag)
     L.append(".Lgpx_run_%s:" % tag)
     # Burst-load the program's remaining 64-byte lines (from the current
-    # record's line up to byte offset s75) into the scalar cache, up to 8
+    # record's line up to byte offset s75) into the scalar cache, up to s78
     # loads in flight, so the handlers' record loads then hit.  s75 = 0 skips
     # it (re-entry after an exit).  s76 only receives data; every load is
     # waited for before the first handler runs.
@@ -494,7 +496,7 @@ def asm_text(T, D, NF, tag, hs):
     L.append("s_load_dword s76, s[60:61], s73")
     L.append("s_add_u32 s73, s73, 64")
     L.append("s_add_u32 s74, s74, 1")
-    L.append("s_cmp_lt_u32 s74, 8")
+    L.append("s_cmp_lt_u32 s74, s78")
     L.append("s_cbranch_scc1 .Lgpx_pf_%s" % tag)
     L.append("s_waitcnt lgkmcnt(0)")
     L.append("s_mov_b32 s74, 0")
@@ -576,13 +578,13 @@ def main(out_dir):
         lines.append("template <> struct Core<%d, %d, %d, %d, %d> {" % (T, D, NF, NCV, core[4]))
         lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")
         lines.append("    // pf_end: byte offset where the program ends (its code is first burst-loaded into the")
-        lines.append("    // scalar cache), or 0")
+        lines.append("    // scalar cache, `burst` loads in flight at a time), or 0")
         lines.append("    static __device__ __forceinline__ void run(uint64_t base, uint32_t& off, uint32_t& pay,"
-                     " uint32_t& cst, uint32_t probe, uint32_t pf_end, uint64_t& table) {")
+                     " uint32_t& cst, uint32_t probe, uint32_t pf_end, uint32_t burst, uint64_t& table) {")
         lines.append("#ifdef __HIP_DEVICE_COMPILE__")
         lines.append('        asm volatile("%s"' % text)
         lines.append('            : "+{s62}"(off), "={s66}"(pay), "={s67}"(cst), "={s[76:77]}"(table)')
-        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe), "{s75}"(pf_end)')
+        lines.append('            : "{s[60:61]}"(base), "{s63}"(probe), "{s75}"(pf_end), "{s78}"(burst)')
         lines.append('            : %s, "s64", "s65", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "scc", "m0",'
                      ' "memory");' % clob_v)
         lines.append("#endif")

