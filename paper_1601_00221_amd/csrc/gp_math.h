@@ -7,20 +7,21 @@
 //
 // Method (table-driven reduction, written from the mathematics; the tables
 // come from gen_math_tables.py):
-//   sin/cos: k = nearest integer to x * 32/pi, j = k mod 64; r = x - k pi/32
-//            with pi/32 in three binary64 parts (the first product is exact
-//            for |x| < 2^19 since x is a binary32 value), |r| <= pi/64;
-//            Taylor series of sin r to r^9 and cos r to r^8; then
-//            sin x = sin(j pi/32) cos r + cos(j pi/32) sin r (and the cosine
-//            likewise) from a 64-entry table.  |x| >= 2^19, inf and NaN go
-//            to the binary64 library function.
+//   sin/cos: k = nearest integer to x * 64/pi, j = k mod 128; r = x - k pi/64
+//            with pi/64 in three binary64 parts (the first product is exact
+//            for |x| < 2^19 since x is a binary32 value), |r| <= pi/128;
+//            Taylor series of sin r to r^7 and cos r to r^6 (the next terms
+//            are below 2^-60 relative); then sin x = sin(j pi/64) cos r +
+//            cos(j pi/64) sin r (and the cosine likewise) from a 128-entry
+//            table.  |x| >= 2^19, inf and NaN go to the binary64 library
+//            function.
 //   exp:     k = nearest integer to 64 x / ln 2 = 64 e + j; r = x - k ln2/64
-//            (two parts), |r| <= ln2/128; Taylor series to r^6; times
-//            2^(j/64) from a table, scaled by 2^e.  Results below the
-//            binary32 range underflow to +0.
+//            (two parts), |r| <= ln2/128; Taylor series to r^5 (the r^6 term
+//            is below 2^-54 relative); times 2^(j/64) from a table, scaled by
+//            2^e.  Results below the binary32 range underflow to +0.
 //   log:     x = f 2^e with f in [sqrt(1/2), sqrt(2)); j = nearest integer
 //            to 128 f; r = f * c - 1 with c = 128/j rounded (|r| <= 1/181);
-//            log f = log1p(r) - log c, the series of log1p to r^8 and
+//            log f = log1p(r) - log c, the series of log1p to r^7 and
 //            -log c from a table in two binary64 parts; plus e ln 2 (two
 //            parts, the first with 45 significant bits so that e * ln2_hi is
 //            exact).  j = 128 gives c = 1 exactly, so log 1 = +0.
@@ -56,28 +57,27 @@ namespace gmath {
 // Offsets of the reduction tables in one contiguous block of doubles.
 enum : int {
     kTabSin = 0,
-    kTabCos = 64,
-    kTabExp = 128,
-    kTabLogInv = 192,
+    kTabCos = 128,
+    kTabExp = 256,
+    kTabLogInv = 320,
     kTabLogHi = kTabLogInv + (GPX_LOG_J1 - GPX_LOG_J0 + 1),
     kTabLogLo = kTabLogHi + (GPX_LOG_J1 - GPX_LOG_J0 + 1),
     kTabSize = kTabLogLo + (GPX_LOG_J1 - GPX_LOG_J0 + 1),
 };
 
-// Series coefficients, one block: sin (r^3 .. r^9), cos (r^2 .. r^8),
-// exp (r^2 .. r^6), log1p (r^2 .. r^8).
-enum : int { kCoSin = 0, kCoCos = 4, kCoExp = 8, kCoLog = 13, kCoSize = 20 };
+// Series coefficients, one block: sin (r^3 .. r^7), cos (r^2 .. r^6),
+// exp (r^2 .. r^5), log1p (r^2 .. r^7).
+enum : int { kCoSin = 0, kCoCos = 3, kCoExp = 6, kCoLog = 10, kCoSize = 16 };
 GPX_TABLE double kCoef[kCoSize] = {
-    // (-1)^k / (2k+1)!, k = 1 .. 4
-    -0x1.5555555555555p-3, 0x1.1111111111111p-7, -0x1.a01a01a01a01ap-13, 0x1.71de3a556c734p-19,
-    // (-1)^k / (2k)!, k = 1 .. 4
-    -0x1.0000000000000p-1, 0x1.5555555555555p-5, -0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-16,
-    // 1 / k!, k = 2 .. 6
+    // (-1)^k / (2k+1)!, k = 1 .. 3
+    -0x1.5555555555555p-3, 0x1.1111111111111p-7, -0x1.a01a01a01a01ap-13,
+    // (-1)^k / (2k)!, k = 1 .. 3
+    -0x1.0000000000000p-1, 0x1.5555555555555p-5, -0x1.6c16c16c16c17p-10,
+    // 1 / k!, k = 2 .. 5
     0x1.0000000000000p-1, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
-    0x1.6c16c16c16c17p-10,
-    // (-1)^(k+1) / k, k = 2 .. 8
+    // (-1)^(k+1) / k, k = 2 .. 7
     -0x1.0000000000000p-1, 0x1.5555555555555p-2, -0x1.0000000000000p-2, 0x1.999999999999ap-3,
-    -0x1.5555555555555p-3, 0x1.2492492492492p-3, -0x1.0000000000000p-3,
+    -0x1.5555555555555p-3, 0x1.2492492492492p-3,
 };
 
 // Copy the reduction tables into one block (the device copies into LDS).
@@ -111,16 +111,16 @@ GPX_HD void sincos_n(float (&a)[N], bool want_cos, const double* tab, int z) {
         x[i] = (double)a[i];
         big[i] = !(fabs(x[i]) < 0x1p19);                        // also inf and NaN
         const double xs = big[i] ? 0.0 : x[i];
-        const double kd = rint(xs * 0x1.45f306dc9c883p+3);      // x * 32/pi
-        double t = fma(-kd, 0x1.921fb54442d18p-4, xs);           // exact
-        t = fma(-kd, 0x1.1a62633145c07p-58, t);
-        r[i] = fma(-kd, -0x1.f1976b7ed8fbcp-114, t);
+        const double kd = rint(xs * 0x1.45f306dc9c883p+4);      // x * 64/pi
+        double t = fma(-kd, 0x1.921fb54442d18p-5, xs);           // exact
+        t = fma(-kd, 0x1.1a62633145c07p-59, t);
+        r[i] = fma(-kd, -0x1.f1976b7ed8fbcp-115, t);
         s[i] = r[i] * r[i];
-        j[i] = (int)kd & 63;
+        j[i] = (int)kd & 127;
     }
     for (int i = 0; i < N; i++) {
-        const double sp = fma(r[i] * s[i], horner(s[i], co + kCoSin, 4), r[i]);   // sin r
-        const double cp = fma(s[i], horner(s[i], co + kCoCos, 4), 1.0);            // cos r
+        const double sp = fma(r[i] * s[i], horner(s[i], co + kCoSin, 3), r[i]);   // sin r
+        const double cp = fma(s[i], horner(s[i], co + kCoCos, 3), 1.0);            // cos r
         const double sj = tab[kTabSin + j[i]], cj = tab[kTabCos + j[i]];
         double v = want_cos ? fma(cj, cp, -(sj * sp)) : fma(sj, cp, cj * sp);
         v = (x[i] == 0.0) ? (want_cos ? 1.0 : x[i]) : v;                           // keeps the sign of a zero
@@ -141,8 +141,8 @@ GPX_HD void expc_n(float (&a)[N], const double* tab, int z) {
         const int k = (int)kd;
         double r = fma(-kd, 0x1.62e42fefa39efp-7, x);            // exact
         r = fma(-kd, 0x1.abc9e3b39803fp-62, r);
-        // e^r = 1 + r + r^2 (1/2 + r/6 + ... + r^4/720)
-        const double p = fma(r, fma(r, horner(r, co + kCoExp, 5), 1.0), 1.0);
+        // e^r = 1 + r + r^2 (1/2 + r/6 + r^2/24 + r^3/120)
+        const double p = fma(r, fma(r, horner(r, co + kCoExp, 4), 1.0), 1.0);
         const double v = ldexp(tab[kTabExp + (k & 63)] * p, k >> 6);
         // below half the least subnormal the result rounds to +0; NaN stays NaN
         a[i] = ok ? (float)v : (t != t ? t : 0.0f);
@@ -165,7 +165,7 @@ GPX_HD void plog_n(float (&a)[N], const double* tab, int z) {
         const double ed = (double)(lo ? e - 1 : e);
         const int q = (int)rint(f * 128.0) - GPX_LOG_J0;
         const double r = fma(f, tab[kTabLogInv + q], -1.0);
-        const double lp = fma(r * r, horner(r, co + kCoLog, 7), r);       // log1p r
+        const double lp = fma(r * r, horner(r, co + kCoLog, 6), r);       // log1p r
         const double hi = fma(ed, 0x1.62e42fefa3900p-1, tab[kTabLogHi + q]);
         const double lw = fma(ed, 0x1.de6af278ece60p-46, tab[kTabLogLo + q]) + lp;
         const float v = (float)(hi + lw);

@@ -100,7 +100,7 @@ def test_tables_regenerate_from_their_definitions(tmp_path):
 
 
 def test_table_spot_values():
-    """A few entries against closed forms: sin(pi/4) = cos(pi/4) = 2^-1/2,
+    """A few entries against closed forms: sin(pi/4) = cos(pi/4) = 2^-1/2 (j = 16),
     2^(32/64) = 2^1/2, and 128/128 = 1 with log 1 = 0."""
     import re
     text = open(os.path.join(ROOT, "paper_1601_00221_amd", "csrc", "gp_math_tables.h")).read()
@@ -109,7 +109,8 @@ def test_table_spot_values():
         body = re.search(name + r"\[\d+\] = \{([^}]*)\}", text).group(1)
         return [float.fromhex(x.strip()) for x in body.split(",") if x.strip()]
     h = float.fromhex("0x1.6a09e667f3bcdp-1")    # nearest binary64 to 2^-1/2
-    assert arr("kSinJ")[8] == h and arr("kCosJ")[8] == h
+    assert arr("kSinJ")[16] == h and arr("kCosJ")[16] == h
+    assert len(arr("kSinJ")) == 128 and arr("kSinJ")[32] == 1.0 and arr("kSinJ")[64] == 0.0 and arr("kCosJ")[0] == 1.0
     assert arr("kExp2J")[32] == float.fromhex("0x1.6a09e667f3bcdp+0")
     j0 = int(re.search(r"GPX_LOG_J0 (\d+)", text).group(1))
     assert arr("kLogInv")[128 - j0] == 1.0 and arr("kLogHi")[128 - j0] == 0.0
