@@ -119,3 +119,34 @@ def test_1d_rejects_before_launch():
     gp.gp_eval_tree_1d(pop.tok, pop.cst, pop.off, X, None, "cases", out2, form="lgp")
     torch.cuda.synchronize()
     assert (out2.cpu().numpy() == 0).all()
+
+
+def test_1d_full_size_against_2d_and_oracle():
+    """The benchmark's scale-tree population (4096 trees x 65,536 cases) in
+    both 1D forms: every program's fitness matches the 2D kernel's up to the
+    summation order, and sampled programs match the oracle."""
+    import torch
+    from tests.gpu_util import well_conditioned_tree
+    w = synth.scale_tree_workload()
+    Xd = dev(w.X)
+    # the first candidate target tree with finite values below 1e6, as the benchmark takes it
+    vals = oracle.tree_outputs(w.target.tok, w.target.cst, w.target.off, w.X)
+    good = [i for i in range(w.target.n_prog) if np.isfinite(vals[i]).all() and np.abs(vals[i]).max() < 1e6]
+    y = (vals[good[0]] + w.noise).astype(np.float32)
+    yd = dev(y)
+    out2 = gp.out_tensor("mse", w.pop.n_prog, 0)
+    gp.gp_eval_tree(w.pop.tok, w.pop.cst, w.pop.off, Xd, yd, "mse", out2)
+    torch.cuda.synchronize()
+    f2 = out2.cpu().numpy()
+    idx = np.linspace(0, w.pop.n_prog - 1, 12).astype(int)
+    sub = w.pop.subset(idx)
+    ref, ok = well_conditioned_tree(sub, w.X, y, "mse")
+    for form in FORMS:
+        say("1d %s full size" % form)
+        out = gp.out_tensor("mse", w.pop.n_prog, 0)
+        gp.gp_eval_tree_1d(w.pop.tok, w.pop.cst, w.pop.off, Xd, yd, "mse", out, form=form)
+        torch.cuda.synchronize()
+        f1 = out.cpu().numpy()
+        assert same_rel(f1, f2, 1e-6).all()
+        close = fitness_close(f1[idx], ref)
+        assert not (~close & ok).any()
