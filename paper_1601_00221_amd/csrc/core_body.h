@@ -47,33 +47,19 @@ template <int T, int V0, bool AR>
 __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits, const double* tab) {
     const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
     const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
-    const float c = __uint_as_float(cbits);
+    // an operand is the instruction's constant (flag set) or T slots of the
+    // core's range; one scalar branch inside the helper picks
     if (op == GP_PDIV) {
         float A[T], B[T];
-        if (fl & 1u) {
-#pragma unroll
-            for (int j = 0; j < T; j++) A[j] = c;
-        } else {
-            core_gather<T, V0>(oa, A);
-        }
-        if (fl & 2u) {
-#pragma unroll
-            for (int j = 0; j < T; j++) B[j] = c;
-        } else {
-            core_gather<T, V0>(ob, B);
-        }
+        core_gather_or_const<T, V0>(oa, fl & 1u, cbits, A);
+        core_gather_or_const<T, V0>(ob, fl & 2u, cbits, B);
 #pragma unroll
         for (int j = 0; j < T; j++) A[j] = pdiv(A[j], B[j]);
         core_scatter<T, V0>(od, A);
         return;
     }
     float A[T];
-    if (fl & 1u) {
-#pragma unroll
-        for (int j = 0; j < T; j++) A[j] = c;
-    } else {
-        core_gather<T, V0>(oa, A);
-    }
+    core_gather_or_const<T, V0>(oa, fl & 1u, cbits, A);
     if constexpr (AR) {
         // arithmetic-only kernel: the host never runs sin/cos/exp/log programs on it
         return;

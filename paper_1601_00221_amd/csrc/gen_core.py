@@ -534,6 +534,18 @@ def gather_scatter(T, V0):
                % (T, movs, outs))
     out.append("#endif")
     out.append("}")
+    # gather, or broadcast the constant when use_const is nonzero: one scalar
+    # branch inside the asm, so the compiler cannot run both paths
+    cmovs = "".join("v_mov_b32_e32 %%%d, %%%d\\n\\t" % (j, T + 2) for j in range(T))
+    gmovs = "".join("v_mov_b32_e32 %%%d, %s\\n\\t" % (j, vr(V0 + j)) for j in range(T))
+    out.append("template <> __device__ __forceinline__ void core_gather_or_const<%s>(uint32_t off, uint32_t use_const, "
+               "uint32_t cbits, float (&v)[%d]) {" % (tv, T))
+    out.append("#ifdef __HIP_DEVICE_COMPILE__")
+    out.append('    asm volatile("s_cmp_eq_u32 %%%d, 0\\n\\ts_cbranch_scc1 1f\\n\\t%ss_branch 2f\\n1:\\n\\t'
+               's_set_gpr_idx_on %%%d, gpr_idx(SRC0)\\n\\t%ss_set_gpr_idx_off\\n2:" : %s : "s"(off), "s"(use_const), '
+               '"s"(cbits) : "m0", "scc");' % (T + 1, cmovs, T, gmovs, outs))
+    out.append("#endif")
+    out.append("}")
     ins = ", ".join('"v"(v[%d])' % j for j in range(T))
     movs = "".join("v_mov_b32_e32 %s, %%%d\\n\\t" % (vr(V0 + j), j + 1) for j in range(T))
     out.append("template <> __device__ __forceinline__ void core_scatter<%s>(uint32_t off, const float (&v)[%d]) {"
@@ -560,6 +572,8 @@ def main(out_dir):
     lines.append("template <int T, int D, int NF, int V0, int K> struct Core;   // K: 0 arithmetic, 2 Boolean, 3 trees only")
     lines.append("template <int T, int V0> __device__ void core_gather(uint32_t off, float (&v)[T]);")
     lines.append("template <int T, int V0> __device__ void core_scatter(uint32_t off, const float (&v)[T]);")
+    lines.append("template <int T, int V0> __device__ void core_gather_or_const(uint32_t off, uint32_t use_const, "
+                 "uint32_t cbits, float (&v)[T]);")
     for T, V0 in sorted(set((v[0], v[3]) for v in VARIANTS)):
         lines.append(gather_scatter(T, V0))
     host = []
