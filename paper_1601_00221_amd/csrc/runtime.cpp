@@ -67,26 +67,28 @@ void DevBuf::release() {
 }
 
 gp_status Staging::begin(size_t n) {
-    if (pending) {
-        hipError_t e = hipEventSynchronize(ev);
+    cur ^= 1;
+    Half& h = half[cur];
+    if (h.pending) {
+        hipError_t e = hipEventSynchronize(h.ev);
         if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
-        pending = false;
+        h.pending = false;
     }
-    if (!ev) {
-        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (!h.ev) {
+        hipError_t e = hipEventCreateWithFlags(&h.ev, hipEventDisableTiming);
         if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
     }
-    if (n > cap) {
-        if (host) hipHostFree(host);
-        host = nullptr;
-        cap = 0;
+    if (n > h.cap) {
+        if (h.host) hipHostFree(h.host);
+        h.host = nullptr;
+        h.cap = 0;
         size_t want = n < 65536 ? 65536 : n + n / 4;
-        hipError_t e = hipHostMalloc(&host, want, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc(&h.host, want, hipHostMallocDefault);
         if (e != hipSuccess) {
-            host = nullptr;
+            h.host = nullptr;
             return fail(GP_E_NOMEM, "hipHostMalloc(%zu): %s", want, hipGetErrorString(e));
         }
-        cap = want;
+        h.cap = want;
     }
     used = 0;
     return GP_OK;
@@ -94,18 +96,31 @@ gp_status Staging::begin(size_t n) {
 
 gp_status Staging::put(const void* src, size_t n, void* dst, hipStream_t s) {
     if (n == 0) return GP_OK;
-    memcpy((char*)host + used, src, n);
-    hipError_t e = hipMemcpyAsync(dst, (char*)host + used, n, hipMemcpyHostToDevice, s);
+    Half& h = half[cur];
+    if (used + n > h.cap) return fail(GP_E_INVAL, "internal: staging overflow (%zu + %zu > %zu)", used, n, h.cap);
+    memcpy((char*)h.host + used, src, n);
+    hipError_t e = hipMemcpyAsync(dst, (char*)h.host + used, n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
     used += (n + 255) & ~(size_t)255;
     return GP_OK;
 }
 
 gp_status Staging::end(hipStream_t s) {
-    hipError_t e = hipEventRecord(ev, s);
+    Half& h = half[cur];
+    hipError_t e = hipEventRecord(h.ev, s);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
-    pending = true;
+    h.pending = true;
     return GP_OK;
+}
+
+void Staging::release() {
+    for (Half& h : half) {
+        if (h.pending && h.ev) hipEventSynchronize(h.ev);
+        if (h.host) hipHostFree(h.host);
+        if (h.ev) hipEventDestroy(h.ev);
+        h = Half();
+    }
+    used = 0;
 }
 
 static std::mutex g_ws_mu;
@@ -283,39 +298,67 @@ static void make_groups(const ProgData& pd, int32_t G, std::vector<uint32_t>& or
     }
 }
 
-static gp_status upload_core(const ProgData& pd, int vi, DevProgs& dp, hipStream_t s, Workspace& w) {
-    std::vector<uint32_t> code;
+// Translate and upload the programs for variant vi (when `fresh` or not yet
+// uploaded) and the group layout for G groups (when not cached), all in one
+// staging pass on stream s, then record dp.ready on s.  One-shot calls
+// (`fresh`) keep a single group layout, replaced on every call.  G <= 0:
+// programs only.
+static gp_status prepare_programs(const ProgData& pd, int vi, DevProgs& dp, bool fresh, int32_t G, hipStream_t s,
+                                  Workspace& w, const uint32_t** order, const uint32_t** goff) {
+    std::vector<uint32_t> code, o, g;
     std::vector<DevProg> progs;
-    gp_status st = core_translate(pd, vi, code, progs);
-    if (st != GP_OK) return st;
-    if ((st = dp.code.reserve(std::max<size_t>(16, code.size() * 4))) != GP_OK) return st;
-    if ((st = dp.progs.reserve(std::max<size_t>(1, progs.size()) * sizeof(DevProg))) != GP_OK) return st;
-    if ((st = w.staging.begin(code.size() * 4 + progs.size() * sizeof(DevProg) + 1024)) != GP_OK) return st;
-    if ((st = w.staging.put(code.data(), code.size() * 4, dp.code.p, s)) != GP_OK) return st;
-    if ((st = w.staging.put(progs.data(), progs.size() * sizeof(DevProg), dp.progs.p, s)) != GP_OK) return st;
-    if ((st = w.staging.end(s)) != GP_OK) return st;
-    dp.groups_by_G.clear();
-    dp.uploaded = true;
-    return GP_OK;
-}
-
-static gp_status groups_for(const ProgData& pd, DevProgs& dp, int32_t G, hipStream_t s, Workspace& w,
-                            const uint32_t** order, const uint32_t** goff) {
-    auto it = dp.groups_by_G.find(G);
-    if (it == dp.groups_by_G.end()) {
-        std::vector<uint32_t> o, g;
-        make_groups(pd, G, o, g);
-        std::unique_ptr<DevBuf> b(new DevBuf());
-        gp_status st;
-        if ((st = b->reserve((o.size() + g.size()) * 4)) != GP_OK) return st;
-        if ((st = w.staging.begin((o.size() + g.size()) * 4 + 512)) != GP_OK) return st;
-        if ((st = w.staging.put(o.data(), o.size() * 4, b->p, s)) != GP_OK) return st;
-        if ((st = w.staging.put(g.data(), g.size() * 4, (uint32_t*)b->p + o.size(), s)) != GP_OK) return st;
-        if ((st = w.staging.end(s)) != GP_OK) return st;
-        it = dp.groups_by_G.emplace(G, std::make_pair((int64_t)o.size(), std::move(b))).first;
+    gp_status st;
+    const bool upload = fresh || !dp.uploaded;
+    if (!upload && dp.ready) {
+        // uploaded earlier, possibly on another stream: order this launch after it
+        hipError_t e = hipStreamWaitEvent(s, dp.ready, 0);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipStreamWaitEvent: %s", hipGetErrorString(e));
     }
-    *order = (const uint32_t*)it->second.second->p;
-    *goff = *order + it->second.first;
+    if (upload && (st = core_translate(pd, vi, code, progs)) != GP_OK) return st;
+    DevBuf* gb = nullptr;
+    int64_t n_order = 0;
+    if (fresh) {
+        gb = &dp.groups_once;
+    } else {
+        auto it = dp.groups_by_G.find(G);
+        if (it != dp.groups_by_G.end()) {
+            gb = &it->second.second;
+            n_order = it->second.first;
+        }
+    }
+    const bool new_groups = G > 0 && (fresh || gb == nullptr);
+    if (new_groups) {
+        make_groups(pd, G, o, g);
+        n_order = (int64_t)o.size();
+        if (!fresh) gb = &dp.groups_by_G.emplace(G, std::make_pair(n_order, DevBuf())).first->second.second;
+        if ((st = gb->reserve((o.size() + g.size()) * 4)) != GP_OK) return st;
+    }
+    if (upload || new_groups) {
+        if (upload) {
+            if ((st = dp.code.reserve(std::max<size_t>(16, code.size() * 4))) != GP_OK) return st;
+            if ((st = dp.progs.reserve(std::max<size_t>(1, progs.size()) * sizeof(DevProg))) != GP_OK) return st;
+        }
+        const size_t bytes = code.size() * 4 + progs.size() * sizeof(DevProg) + (o.size() + g.size()) * 4 + 1024;
+        if ((st = w.staging.begin(bytes)) != GP_OK) return st;
+        if (upload) {
+            if ((st = w.staging.put(code.data(), code.size() * 4, dp.code.p, s)) != GP_OK) return st;
+            if ((st = w.staging.put(progs.data(), progs.size() * sizeof(DevProg), dp.progs.p, s)) != GP_OK) return st;
+        }
+        if (new_groups) {
+            if ((st = w.staging.put(o.data(), o.size() * 4, gb->p, s)) != GP_OK) return st;
+            if ((st = w.staging.put(g.data(), g.size() * 4, (uint32_t*)gb->p + o.size(), s)) != GP_OK) return st;
+        }
+        if ((st = w.staging.end(s)) != GP_OK) return st;
+        if (!dp.ready) {
+            hipError_t e = hipEventCreateWithFlags(&dp.ready, hipEventDisableTiming);
+            if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        }
+        hipError_t e = hipEventRecord(dp.ready, s);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+        dp.uploaded = true;
+    }
+    if (order) *order = gb ? (const uint32_t*)gb->p : nullptr;
+    if (goff) *goff = gb ? (const uint32_t*)gb->p + n_order : nullptr;
     return GP_OK;
 }
 
@@ -406,6 +449,11 @@ hipError_t timed_launch_end(hipStream_t s, int slot) {
     return hipEventRecord(g_tm_events[slot].second, s);
 }
 
+int default_variant(const ProgData& pd) {
+    return pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0,
+                             pd.n_transc > 0, pd.opset == OPSET_BOOL, pd.form == FORM_TREE);
+}
+
 gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
                     int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
                     const EvalOptions* opt, int64_t n_bits) {
@@ -422,10 +470,7 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     if (boolean != (n_bits > 0)) return fail(GP_E_INVAL, "internal: Boolean programs need a bit count");
     if (boolean && kind != GP_FIT_HITS && kind != GP_OUT_CASES)
         return fail(GP_E_INVAL, "Boolean programs take GP_FIT_HITS or GP_OUT_CASES, not kind %d", kind);
-    const int vi = opt && opt->variant >= 0
-                       ? opt->variant
-                       : pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0,
-                                           pd.n_transc > 0, boolean, pd.form == FORM_TREE);
+    const int vi = opt && opt->variant >= 0 ? opt->variant : default_variant(pd);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth ||
@@ -435,8 +480,6 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     gp_status st;
     if ((st = core_ready(vi, s)) != GP_OK) return st;
     DevProgs& dp = dps[vi];
-    if (fresh || !dp.uploaded)
-        if ((st = upload_core(pd, vi, dp, s, w)) != GP_OK) return st;
     const int T = core_variant_t(vi);
     const int64_t tiles64 = (N + 64LL * T - 1) / (64LL * T);
     if (tiles64 > (1LL << 30)) return fail(GP_E_INVAL, "n_cases too large");
@@ -447,7 +490,7 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     const int64_t units = same_group ? (int64_t)G * ((L.chunks + 3) / 4) : (int64_t)L.chunks * ((G + 3) / 4);
     if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
     const uint32_t *order, *goff;
-    if ((st = groups_for(pd, dp, G, s, w, &order, &goff)) != GP_OK) return st;
+    if ((st = prepare_programs(pd, vi, dp, fresh, G, s, w, &order, &goff)) != GP_OK) return st;
     const int64_t n_blocks = (N + 255) / 256;
     if (kind != GP_OUT_CASES) {
         if ((st = w.partials.reserve((size_t)n_blocks * pd.n_prog * sizeof(double))) != GP_OK) return st;
@@ -560,9 +603,21 @@ gp_status gp_eval_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, c
 }
 
 static gp_status progset_finish(ProgData&& pd, void* stream, gp_progset** ps) {
-    (void)stream;   // programs are translated and uploaded on first evaluation, per kernel variant
+    // Translate the programs for the kernel variant evaluations will use and
+    // upload them on `stream` now; an evaluation on any stream waits for it.
     std::unique_ptr<gp_progset> p(new gp_progset());
     p->pd = std::move(pd);
+    if (p->pd.n_prog > 0) {
+        const int vi = default_variant(p->pd);
+        if (vi < 0) return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", p->pd.n_load,
+                                p->pd.max_depth);
+        hipStream_t s = (hipStream_t)stream;
+        gp_status st;
+        if ((st = core_ready(vi, s)) != GP_OK) return st;
+        Workspace& w = workspace(s);
+        std::lock_guard<std::mutex> g(w.mu);
+        if ((st = prepare_programs(p->pd, vi, p->dps[vi], false, 0, s, w, nullptr, nullptr)) != GP_OK) return st;
+    }
     *ps = p.release();
     return GP_OK;
 }
@@ -625,9 +680,7 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->max_depth = ps->pd.max_depth;
     info->n_instr = ps->pd.n_instr;
     info->n_gpop = ps->pd.n_gpop;
-    info->variant = pick_core_variant(ps->pd.n_load, ps->pd.max_depth,
-                                      ps->pd.n_instr ? (double)ps->pd.n_transc / ps->pd.n_instr : 0.0,
-                                      ps->pd.n_transc > 0, ps->pd.opset == OPSET_BOOL, ps->pd.form == FORM_TREE);
+    info->variant = default_variant(ps->pd);
     info->pad = 0;
     return GP_OK;
 }

@@ -20,25 +20,48 @@ gp_status fail(gp_status s, const char* fmt, ...) __attribute__((format(printf, 
 void clear_error();
 const char* last_error();
 
-// Grow-only device buffer.
+// Grow-only device buffer.  It owns its allocation: moving hands it over,
+// destruction frees it.
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            cap = o.cap;
+            o.p = nullptr;
+            o.cap = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
     gp_status reserve(size_t n);
     void release();
 };
 
-// Pinned host staging for host-to-device copies.  begin() waits until the
-// copies of the previous use have left the buffer.
+// Pinned host staging for host-to-device copies, in two halves used in
+// turn: begin() takes the other half and waits only until the copies of
+// that half's previous use (two uses ago) have left it, so a call does not
+// wait for its own copies or for the kernels queued before them.
 struct Staging {
-    void* host = nullptr;
-    size_t cap = 0;
+    struct Half {
+        void* host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Half half[2];
+    int cur = 0;
     size_t used = 0;
-    hipEvent_t ev = nullptr;
-    bool pending = false;
     gp_status begin(size_t n);
     gp_status put(const void* src, size_t n, void* dst, hipStream_t s);
     gp_status end(hipStream_t s);
+    void release();
 };
 
 // Lowered programs on the host.
@@ -58,19 +81,29 @@ struct ProgData {
     std::vector<uint32_t> cost;
 };
 
-// Device copies of programs translated for one core variant, plus cached
-// group layouts.
+// Device copies of programs translated for one core variant, plus their
+// group layouts (program order and group offsets) by group count.  `ready`
+// is recorded on the stream of the last upload into these buffers; a launch
+// on any stream waits for it.
 struct DevProgs {
     bool uploaded = false;
     DevBuf code;
     DevBuf progs;
-    std::map<int32_t, std::pair<int64_t, std::unique_ptr<DevBuf>>> groups_by_G;
+    std::map<int32_t, std::pair<int64_t, DevBuf>> groups_by_G;
+    DevBuf groups_once;        // one-shot calls: the group layout of the current programs
+    hipEvent_t ready = nullptr;
+    DevProgs() = default;
+    DevProgs(const DevProgs&) = delete;
+    DevProgs& operator=(const DevProgs&) = delete;
+    ~DevProgs() { release(); }
     void release() {
         uploaded = false;
         code.release();
         progs.release();
-        for (auto& kv : groups_by_G) kv.second.second->release();
         groups_by_G.clear();
+        groups_once.release();
+        if (ready) hipEventDestroy(ready);
+        ready = nullptr;
     }
 };
 
@@ -101,6 +134,8 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
                      ProgData& pd, int opset = OPSET_REAL);
 gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
                        int32_t P, int32_t n_reg, int32_t n_feat, ProgData& pd);
+// The kernel variant an evaluation of these programs uses by default.
+int default_variant(const ProgData& pd);
 // Evaluate lowered programs on one case matrix.  dps caches the programs
 // translated per core variant; fresh forces a new translation and upload.
 // Boolean programs (pd.opset == OPSET_BOOL) take X and y as 32-bit words, N

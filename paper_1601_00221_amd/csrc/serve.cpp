@@ -468,8 +468,7 @@ gp_status gp_serve_destroy(gp_server* sv) {
         sc->code.release(); sc->progs.release(); sc->order.release(); sc->units.release();
         sc->jobs.release(); sc->datasets.release(); sc->reduce.release(); sc->partials.release();
         sc->counter.release();
-        if (sc->staging.host) hipHostFree(sc->staging.host);
-        if (sc->staging.ev) hipEventDestroy(sc->staging.ev);
+        sc->staging.release();
     }
     delete sv;
     return GP_OK;

@@ -9,7 +9,8 @@ import pytest
 import oracle
 import paper_1601_00221_amd as gp
 import synth
-from tests.gpu_util import dev, fitness_close, gpu_linear, gpu_tree, has_transcendental_tree, say
+from tests.gpu_util import (dev, fitness_close, gpu_linear, gpu_tree, has_transcendental_tree, say,
+                            well_conditioned_tree)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +43,26 @@ def _alone(pop, X, y, kind):
     if hasattr(pop, "tok"):
         return gpu_tree(pop, X, y, kind)
     return gpu_linear(pop, X, y, kind)
+
+
+def _check_oracle(pop, X, y, kind, got):
+    """The fitness contract against the oracle: hit counts exact; sums within
+    the tolerance, except for trees whose oracle fitness moves by more than
+    the tolerance when every sin/cos/exp/log result moves by 2 ulp
+    (ill-conditioned; at most 2 % of a population).  Returns the number of
+    ill-conditioned programs."""
+    if hasattr(pop, "tok"):
+        ref, ok = well_conditioned_tree(pop, X, y, kind)
+        good = fitness_close(got, ref)
+        assert good[ok].all(), (np.flatnonzero(ok & ~good)[:5], got[ok & ~good][:5], ref[ok & ~good][:5])
+        assert (~ok).mean() <= 0.02
+        return int((~ok).sum())
+    ref = oracle.eval_linear(pop.code, pop.off, pop.cst, pop.cst_off, pop.n_reg, X, y, kind, threads=8)
+    if kind == "hits":
+        assert np.array_equal(got, ref)
+    else:
+        assert fitness_close(got, ref).all()
+    return 0
 
 
 def test_batch_matches_individual_evaluation_bit_for_bit():
@@ -168,8 +189,15 @@ def test_served_results_equal_alone_and_in_the_mix(batching):
     say(st)
     srv.close()
     assert not errors
+    ill = 0
     for k, o in enumerate(outs):
-        assert np.array_equal(o.cpu().numpy().view(np.int32), ref[k].view(np.int32)), k
+        got = o.cpu().numpy()
+        # the same bits as the request evaluated alone ...
+        assert np.array_equal(got.view(np.int32), ref[k].view(np.int32)), k
+        # ... and the oracle's fitness within the contract
+        pop, ds, kind = spec[k]
+        ill += _check_oracle(pop, data[ds][0], data[ds][1], kind, got)
+    say("served requests checked against the oracle; ill-conditioned programs:", ill)
     assert st["completed"] == len(spec)
     if not batching:
         assert st["mean_batch"] == 1.0
@@ -192,8 +220,10 @@ def test_served_under_tight_memory_budget():
     torch.cuda.synchronize()
     st = srv.stats()
     srv.close()
-    for o, r in zip(outs, ref):
-        assert np.array_equal(o.cpu().numpy(), r)
+    for o, r, p in zip(outs, ref, pops):
+        got = o.cpu().numpy()
+        assert np.array_equal(got, r)
+        _check_oracle(p, data[0][0], data[0][1], "mse", got)
     assert st["completed"] == 12
 
 
@@ -226,3 +256,55 @@ def test_every_variant_on_arithmetic_programs():
         torch.cuda.synchronize()
         assert fitness_close(out_t.cpu().numpy(), ref_t).all()
         assert fitness_close(out_l.cpu().numpy(), ref_l).all()
+
+
+@pytest.mark.slow
+def test_full_batched_workload_sampled():
+    """The batched workload at full size (10,000 programs in 40 populations of
+    trees and register programs, lengths up to 1024, over matrices of 4096,
+    65,536 and 1,048,576 cases) in one launch with the stored or default
+    configuration; sampled programs of every population checked against the
+    oracle over all cases, including the longest tree and the longest
+    register program on the 1,048,576-case matrix."""
+    import torch
+    w = synth.batched_workload()
+    ys = []
+    for X, tgt, noise in zip(w.X, w.target, w.noise):
+        t = None
+        for i in range(tgt.n_prog):
+            tt = tgt.subset([i])
+            v = oracle.tree_outputs(tt.tok, tt.cst, tt.off, X)[0]
+            if np.all(np.isfinite(v)) and np.all(np.abs(v) < 1e6):
+                t = v
+                break
+        assert t is not None
+        ys.append((t + noise).astype(np.float32))
+    dd = [(dev(X), dev(y)) for X, y in zip(w.X, ys)]
+    outs = [gp.out_tensor(j.kind, j.pop.n_prog, 0) for j in w.jobs]
+    jobs = [gp.make_job(j.pop, j.dataset, j.kind, o) for j, o in zip(w.jobs, outs)]
+    say("full batched workload: one launch")
+    gp.gp_eval_batch(dd, jobs)
+    torch.cuda.synchronize()
+    big = len(w.X) - 1
+    longest = {}
+    for ji, j in enumerate(w.jobs):
+        if j.dataset == big:
+            form = hasattr(j.pop, "tok")
+            sz = j.pop.sizes()
+            k = int(np.argmax(sz))
+            if form not in longest or sz[k] > longest[form][2]:
+                longest[form] = (ji, k, int(sz[k]))
+    assert set(longest) == {True, False}
+    assert all(v[2] >= 900 for v in longest.values()), longest
+    ill = 0
+    for ji, (j, o) in enumerate(zip(w.jobs, outs)):
+        got = o.cpu().numpy()
+        # a program over the 1M-case matrix costs the oracle seconds: one per population there
+        pick = [0] if j.dataset == big else [0, j.pop.n_prog // 4, j.pop.n_prog // 2, 3 * j.pop.n_prog // 4]
+        for v in longest.values():
+            if v[0] == ji:
+                pick.append(v[1])
+        pick = sorted(set(pick))
+        say("job", ji, "dataset", j.dataset, "programs", pick)
+        ill += _check_oracle(j.pop.subset(pick), w.X[j.dataset], ys[j.dataset], j.kind, got[pick])
+    say("ill-conditioned sampled programs:", ill)

@@ -270,6 +270,62 @@ def test_progset_reuse_and_several_datasets():
     ps.close()
 
 
+def test_progset_uploaded_on_one_stream_evaluated_on_another():
+    """A program set is uploaded on the stream it is created on; evaluations
+    on other streams are ordered after that upload."""
+    import torch
+    rng = synth.rng_for(29)
+    pop = synth.ptc2_population(rng, 300, synth.BASIC, 6, 1, 200, 0.2)
+    n = 20000
+    X = synth.uniform_cases(rng, 6, n, -2, 2)
+    y = synth.gaussian_noise(rng, n, 1.0)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    ref = oracle.eval_tree(pop.tok, pop.cst, pop.off, X, y, "mse", threads=8)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    # keep stream A busy so that a missing dependency would show
+    big = torch.randn(4096, 4096, device="cuda")
+    with torch.cuda.stream(sa):
+        for _ in range(4):
+            big = big @ big * 1e-3
+        ps = gp.ProgSet.tree(pop.tok, pop.cst, pop.off, 6, stream=sa)
+    outs = []
+    for s in (sb, sa, sb):
+        o = gp.out_tensor("mse", pop.n_prog, n)
+        with torch.cuda.stream(s):
+            ps.eval(Xd, yd, "mse", o, stream=s)
+        outs.append(o)
+    torch.cuda.synchronize()
+    say("progset across streams")
+    for o in outs:
+        assert fitness_close(o.cpu().numpy(), ref).all()
+    ps.close()
+
+
+def test_one_shot_calls_do_not_leak_device_memory():
+    """Repeated one-shot evaluations reuse the library's buffers: free device
+    memory is the same after 50 more calls."""
+    import torch
+    rng = synth.rng_for(31)
+    pop = synth.ptc2_population(rng, 200, synth.BASIC, 4, 1, 100, 0.2)
+    n = 3000
+    X = synth.uniform_cases(rng, 4, n, -2, 2)
+    y = synth.gaussian_noise(rng, n, 1.0)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    out = gp.out_tensor("mse", pop.n_prog, n)
+    for _ in range(5):
+        gp.gp_eval_tree(pop.tok, pop.cst, pop.off, Xd, yd, "mse", out)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(50):
+        gp.gp_eval_tree(pop.tok, pop.cst, pop.off, Xd, yd, "mse", out)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("free device memory before/after 50 calls:", free0, free1)
+    assert free1 == free0
+    ref = oracle.eval_tree(pop.tok, pop.cst, pop.off, X, y, "mse")
+    assert fitness_close(out.cpu().numpy(), ref).all()
+
+
 # --------------------------------------------------------------------------
 # Full-size workloads, sampled programs
 # --------------------------------------------------------------------------
