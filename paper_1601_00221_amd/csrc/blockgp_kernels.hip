@@ -46,7 +46,7 @@ __device__ __forceinline__ double bg_block_sum(double v, double* red) {
 template <int FORM>
 __global__ __launch_bounds__(256) void k_blockgp(BgArgs a) {
     extern __shared__ uint32_t lds[];
-    __shared__ double s_tab[gmath::kTabSize];
+    __shared__ __attribute__((aligned(16))) double s_tab[gmath::kTabSize];
     __shared__ double red[4];
     gmath::tab_fill(s_tab, (int)threadIdx.x, (int)blockDim.x);
     const int p = blockIdx.x;

@@ -215,7 +215,7 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
     // the transcendentals' reduction tables, copied into LDS by the whole block
     const double* tab = nullptr;
     if constexpr (MODE == 0) {
-        __shared__ double s_tab[gmath::kTabSize];
+        __shared__ __attribute__((aligned(16))) double s_tab[gmath::kTabSize];
         gmath::tab_fill(s_tab, (int)threadIdx.x, (int)blockDim.x);
         __syncthreads();
         tab = s_tab;

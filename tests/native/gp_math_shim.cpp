@@ -5,7 +5,7 @@
 #include "gp_math.h"
 
 namespace {
-double g_tab[gpx::gmath::kTabSize];
+alignas(16) double g_tab[gpx::gmath::kTabSize];
 bool g_ready = false;
 
 template <int N>

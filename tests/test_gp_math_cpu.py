@@ -100,17 +100,30 @@ def test_tables_regenerate_from_their_definitions(tmp_path):
 
 
 def test_table_spot_values():
-    """A few entries against closed forms: sin(pi/4) = cos(pi/4) = 2^-1/2 (j = 16),
-    2^(32/64) = 2^1/2, and 128/128 = 1 with log 1 = 0."""
+    """Entries against closed forms: sin(pi/4) = cos(pi/4) = 2^-1/2 (j = 16),
+    sin(pi/2) = 1 and cos(pi/2) = 0 (j = 32), 2^(32/64) = 2^1/2, the bucket
+    centre 1 with c = 1 and -log c = 0, and the chunks of 64/pi summing to
+    64/pi."""
     import re
+    import mpmath
     text = open(os.path.join(ROOT, "paper_1601_00221_amd", "csrc", "gp_math_tables.h")).read()
 
     def arr(name):
         body = re.search(name + r"\[\d+\] = \{([^}]*)\}", text).group(1)
         return [float.fromhex(x.strip()) for x in body.split(",") if x.strip()]
     h = float.fromhex("0x1.6a09e667f3bcdp-1")    # nearest binary64 to 2^-1/2
-    assert arr("kSinJ")[16] == h and arr("kCosJ")[16] == h
-    assert len(arr("kSinJ")) == 128 and arr("kSinJ")[32] == 1.0 and arr("kSinJ")[64] == 0.0 and arr("kCosJ")[0] == 1.0
+    sc = arr("kSinCos")
+    assert len(sc) == 256 and sc[2 * 16] == h and sc[2 * 16 + 1] == h
+    assert sc[0] == 0.0 and sc[1] == 1.0 and sc[2 * 32] == 1.0 and sc[2 * 32 + 1] == 0.0 and sc[2 * 64] == 0.0
     assert arr("kExp2J")[32] == float.fromhex("0x1.6a09e667f3bcdp+0")
-    j0 = int(re.search(r"GPX_LOG_J0 (\d+)", text).group(1))
-    assert arr("kLogInv")[128 - j0] == 1.0 and arr("kLogHi")[128 - j0] == 0.0
+    k0 = int(re.search(r"GPX_LOG_K0 0x([0-9A-F]+)", text).group(1), 16)
+    ct = arr("kLogCT")
+    one = 0x3F800000 >> 15      # the bucket whose centre is 1.0
+    assert ct[2 * (one - k0)] == 1.0 and ct[2 * (one - k0) + 1] == 0.0
+    chunks = arr("kPiChunks")
+    mpmath.mp.prec = 300
+    total = sum(mpmath.mpf(c) for c in chunks)
+    assert abs(total - 64 / mpmath.pi) < mpmath.mpf(2) ** -210
+    for c in chunks:     # at most 28 significant bits: exact products with binary32 values
+        m, e = mpmath.frexp(mpmath.mpf(c))
+        assert (m * 2 ** 28) == int(m * 2 ** 28)
