@@ -247,6 +247,23 @@ gp_status gp_progset_bool(const int32_t* tok, const int64_t* off, int32_t n_prog
 /* Evaluate a resident set on a case matrix with n_feat >= the set's n_feat. */
 gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases,
                           const float* y, int32_t kind, void* out, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as gp_progset_eval, bit for bit, with nothing allocated and
+ * nothing copied from the host during the call -- it launches the evaluation
+ * and reduction kernels on `stream` and returns.  The programs and their
+ * layout were uploaded when the set was created (on this device).  The
+ * per-(program, 256-case block) partial sums go to a fixed device array of
+ * GP_NOALLOC_MAX_PARTIALS doubles (16 MiB) that each GPU the library runs on
+ * holds until the process ends: n_prog * ceil(n_cases / 256) (Boolean sets:
+ * ceil(n_cases / 8192)) must not exceed it, else GP_E_NOMEM and nothing is
+ * launched; GP_OUT_CASES needs none.  Every call on one GPU shares that
+ * array and leaves its partial sums there: calls that overlap on one GPU
+ * (different streams or threads without ordering between them) race and may
+ * return wrong fitness values.  Calls in order on one stream are safe. */
+#define GP_NOALLOC_MAX_PARTIALS 2097152
+gp_status gp_progset_eval_noalloc(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases,
+                                  const float* y, int32_t kind, void* out, void* stream);
 gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info);
 /* Waits for the device to finish with the set, then frees it. */
 gp_status gp_progset_destroy(gp_progset* ps);

@@ -134,6 +134,7 @@ def lib():
             "gp_progset_linear": [P, P, P, P, i32, i32, i32, P, P],
             "gp_progset_bool": [P, P, i32, i32, P, P],
             "gp_progset_eval": [P, P, i32, i64, P, i32, P, P],
+            "gp_progset_eval_noalloc": [P, P, i32, i64, P, i32, P, P],
             "gp_progset_get_info": [P, P],
             "gp_progset_destroy": [P],
             "gp_lower_tree": [P, P, i64, i32, P, i64, P],
@@ -301,6 +302,12 @@ class ProgSet:
         n = int(X.shape[1]) if n_cases is None else int(n_cases)
         check(lib().gp_progset_eval(self._h, dptr(X), int(X.shape[0]), n, dptr(y),
                                     kind_id(kind), dptr(out), stream_ptr(stream)))
+
+    def eval_noalloc(self, X, y, kind, out, stream=None, n_cases=None):
+        """gp_progset_eval_noalloc: the same evaluation with nothing allocated."""
+        n = int(X.shape[1]) if n_cases is None else int(n_cases)
+        check(lib().gp_progset_eval_noalloc(self._h, dptr(X), int(X.shape[0]), n, dptr(y),
+                                            kind_id(kind), dptr(out), stream_ptr(stream)))
 
     def info(self) -> dict:
         i = ProgsetInfo()

@@ -25,7 +25,7 @@ LIB = os.path.join(PKG, "libgp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["lower.cpp", "runtime.cpp", "batch.cpp", "serve.cpp", "core_host.cpp", "core_kernels.hip",
-           "blockgp.cpp", "blockgp_kernels.hip", "evolve.cpp"]
+           "blockgp.cpp", "blockgp_kernels.hip", "evolve.cpp", "noalloc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

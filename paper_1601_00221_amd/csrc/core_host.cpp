@@ -112,6 +112,13 @@ gp_status core_ready(int vi, hipStream_t s) {
     return GP_OK;
 }
 
+bool core_is_ready(int vi) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> g(g_mu);
+    return vi >= 0 && vi < (int)g_maps.size() && g_maps[vi].ready && g_maps[vi].device == dev;
+}
+
 namespace {
 
 // Handlers come in two phases (records are fetched two at a time, see

@@ -31,6 +31,8 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
 // Locate the variant's handler table on the current device (one probe launch
 // on stream s the first time).
 gp_status core_ready(int vi, hipStream_t s);
+// True if core_ready has found variant vi's handler table on the current device.
+bool core_is_ready(int vi);
 // Core instructions and per-program records of lowered programs.
 gp_status core_translate(const ProgData& pd, int vi, std::vector<uint32_t>& code, std::vector<DevProg>& progs);
 // The same with the handler table taken to start at `base` (no device needed).

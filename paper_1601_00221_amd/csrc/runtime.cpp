@@ -390,7 +390,7 @@ int32_t code_prefetch() {
     return n <= 0 ? 0 : (n > 15 ? 15 : (int32_t)n);
 }
 
-static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOptions* opt) {
+static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOptions* opt, int32_t force_G = 0) {
     // Program groups of about 1024 core instructions when over a fifth of them are sin/cos/exp/log
     // (the exits' compiled code dominates), else 4096 (measured on the 4096-program workloads: 1-2 %
     // better than 2048 either way).
@@ -401,6 +401,7 @@ static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOpt
     int64_t G = (pd.n_instr + group_instr - 1) / group_instr;
     if (((G + 3) / 4) * tiles < target_blocks) G = 4 * ((target_blocks + tiles - 1) / tiles);
     G = std::max<int64_t>(1, std::min<int64_t>(G, pd.n_prog));
+    if (force_G > 0) G = force_G;
     const int64_t quads = (G + 3) / 4;
     int32_t tpw = opt && opt->tiles_per_wave > 0 ? opt->tiles_per_wave : env_int("GP2D_TILES_PER_WAVE", 0);
     if (tpw <= 0) {
@@ -449,13 +450,15 @@ hipError_t timed_launch_end(hipStream_t s, int slot) {
     return hipEventRecord(g_tm_events[slot].second, s);
 }
 
+int32_t base_groups(const ProgData& pd) { return launch_shape(pd, 1 << 30, nullptr).G; }
+
 int default_variant(const ProgData& pd) {
     return pick_core_variant(pd.n_load, pd.max_depth, pd.n_instr ? (double)pd.n_transc / pd.n_instr : 0.0,
                              pd.n_transc > 0, pd.opset == OPSET_BOOL, pd.form == FORM_TREE);
 }
 
 gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
-                    int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
+                    int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace* w,
                     const EvalOptions* opt, int64_t n_bits) {
     if (!X) return fail(GP_E_INVAL, "X is null");
     if (!out) return fail(GP_E_INVAL, "out is null");
@@ -477,23 +480,47 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
         (core_variant_arith(vi) && pd.n_transc > 0) || core_variant_bool(vi) != boolean ||
         (core_variant_trees_only(vi) && pd.form != FORM_TREE))
         return fail(GP_E_INVAL, "variant %d cannot hold these programs", vi);
+    const bool no_alloc = opt && opt->no_alloc;
     gp_status st;
-    if ((st = core_ready(vi, s)) != GP_OK) return st;
-    DevProgs& dp = dps[vi];
+    if (no_alloc) {
+        if (!core_is_ready(vi)) return fail(GP_E_DEVICE, "kernel variant %d is not set up on this device", vi);
+    } else if ((st = core_ready(vi, s)) != GP_OK) {
+        return st;
+    }
+    auto dit = dps.find(vi);
+    if (no_alloc && dit == dps.end()) return fail(GP_E_INVAL, "programs are not on the device for variant %d", vi);
+    DevProgs& dp = no_alloc ? dit->second : dps[vi];
     const int T = core_variant_t(vi);
     const int64_t tiles64 = (N + 64LL * T - 1) / (64LL * T);
     if (tiles64 > (1LL << 30)) return fail(GP_E_INVAL, "n_cases too large");
     const int32_t tiles = (int32_t)tiles64;
-    const LaunchShape L = launch_shape(pd, tiles, opt);
+    const LaunchShape L = launch_shape(pd, tiles, opt, no_alloc ? opt->groups : 0);
     const int32_t G = L.G;
     const int32_t same_group = env_int("GP2D_SAME_GROUP", 0) > 0 ? 1 : 0;
     const int64_t units = same_group ? (int64_t)G * ((L.chunks + 3) / 4) : (int64_t)L.chunks * ((G + 3) / 4);
     if (units > (1LL << 31) - 64) return fail(GP_E_INVAL, "too many work units");
-    const uint32_t *order, *goff;
-    if ((st = prepare_programs(pd, vi, dp, fresh, G, s, w, &order, &goff)) != GP_OK) return st;
     const int64_t n_blocks = (N + 255) / 256;
-    if (kind != GP_OUT_CASES) {
-        if ((st = w.partials.reserve((size_t)n_blocks * pd.n_prog * sizeof(double))) != GP_OK) return st;
+    const size_t part_bytes = kind == GP_OUT_CASES ? 0 : (size_t)n_blocks * pd.n_prog * sizeof(double);
+    const uint32_t *order, *goff;
+    double* partials = nullptr;
+    if (no_alloc) {
+        auto git = dp.groups_by_G.find(G);
+        if (!dp.uploaded || git == dp.groups_by_G.end() || !dp.ready)
+            return fail(GP_E_INVAL, "programs or their group layout are not on the device");
+        if (part_bytes > opt->partials_bytes)
+            return fail(GP_E_NOMEM, "%lld programs x %lld blocks of 256 cases need %zu bytes of partial sums; "
+                        "this entry point has %zu", (long long)pd.n_prog, (long long)n_blocks, part_bytes,
+                        opt->partials_bytes);
+        hipError_t e = hipStreamWaitEvent(s, dp.ready, 0);
+        if (e != hipSuccess) return fail(GP_E_DEVICE, "hipStreamWaitEvent: %s", hipGetErrorString(e));
+        order = (const uint32_t*)git->second.second.p;
+        goff = order + git->second.first;
+        partials = opt->partials;
+    } else {
+        if (!w) return fail(GP_E_INVAL, "internal: no workspace");
+        if ((st = prepare_programs(pd, vi, dp, fresh, G, s, *w, &order, &goff)) != GP_OK) return st;
+        if (part_bytes && (st = w->partials.reserve(part_bytes)) != GP_OK) return st;
+        partials = (double*)w->partials.p;
     }
     CoreArgs a;
     memset(&a, 0, sizeof a);
@@ -514,19 +541,19 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     a.n_groups = G;
     a.same_group = same_group;
     a.n_bits = n_bits;
-    a.partials = (double*)w.partials.p;
+    a.partials = partials;
     a.cases_out = kind == GP_OUT_CASES ? (float*)out : nullptr;
     uint32_t blocks = (uint32_t)units;
     blocks = (blocks + 7u) & ~7u;
-    int slot;
-    hipError_t e = timed_launch_begin(s, &slot);
+    int slot = -1;
+    hipError_t e = no_alloc ? hipSuccess : timed_launch_begin(s, &slot);
     if (e == hipSuccess) e = core_launch(vi, a, blocks, s);
     if (e == hipSuccess) e = timed_launch_end(s, slot);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "evaluation launch: %s", hipGetErrorString(e));
     if (kind == GP_OUT_CASES) return GP_OK;
     ReduceArgs r;
     memset(&r, 0, sizeof r);
-    r.partials = (const double*)w.partials.p;
+    r.partials = partials;
     r.part_base = 0;
     r.n_prog = pd.n_prog;
     r.N = N;
@@ -547,9 +574,29 @@ using namespace gpx;
 
 struct gp_progset {
     ProgData pd;
-    std::map<int, DevProgs> dps;   // translated per core variant, uploaded on first use
+    std::map<int, DevProgs> dps;   // translated per core variant
+    int32_t groups = 0;            // the group layout uploaded at creation
     std::mutex mu;
 };
+
+// Evaluate a program set with nothing allocated or uploaded (see runtime.h).
+gp_status gpx::progset_eval_no_alloc(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                                int32_t kind, void* out, hipStream_t s, double* partials, size_t partials_bytes) {
+    if (!ps) return fail(GP_E_INVAL, "ps is null");
+    std::lock_guard<std::mutex> g(ps->mu);
+    EvalOptions o;
+    o.no_alloc = true;
+    o.groups = ps->groups;
+    o.partials = partials;
+    o.partials_bytes = partials_bytes;
+    if (ps->pd.opset == OPSET_BOOL) {
+        if (n_cases < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
+        if (n_cases > 0x7FFFFFFF) return fail(GP_E_INVAL, "n_cases above 2^31 - 1 (hit counts are int32)");
+        return eval_core(ps->pd, ps->dps, false, X, n_feat, (n_cases + 31) / 32, y, kind, out, s, nullptr, &o,
+                         n_cases);
+    }
+    return eval_core(ps->pd, ps->dps, false, X, n_feat, n_cases, y, kind, out, s, nullptr, &o);
+}
 
 extern "C" {
 
@@ -567,7 +614,7 @@ gp_status gp_eval_tree(const int32_t* tok, const float* cst, const int64_t* off,
     hipStream_t s = (hipStream_t)stream;
     Workspace& w = workspace(s);
     std::lock_guard<std::mutex> g(w.mu);
-    return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+    return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, &w, nullptr);
 }
 
 gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* cst, const int64_t* cst_off,
@@ -580,7 +627,7 @@ gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* 
     hipStream_t s = (hipStream_t)stream;
     Workspace& w = workspace(s);
     std::lock_guard<std::mutex> g(w.mu);
-    return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+    return eval_core(pd, w.oneshot, true, X, n_feat, n_cases, y, kind, out, s, &w, nullptr);
 }
 
 gp_status gp_eval_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, const uint32_t* X, int32_t n_feat,
@@ -598,7 +645,7 @@ gp_status gp_eval_bool(const int32_t* tok, const int64_t* off, int32_t n_prog, c
     std::lock_guard<std::mutex> g(w.mu);
     // one slot per 32-bit word: the kernel sees n_words "cases"
     const int64_t n_words = (n_cases + 31) / 32;
-    return eval_core(pd, w.oneshot, true, (const float*)X, n_feat, n_words, (const float*)y, kind, out, s, w,
+    return eval_core(pd, w.oneshot, true, (const float*)X, n_feat, n_words, (const float*)y, kind, out, s, &w,
                      nullptr, n_cases);
 }
 
@@ -616,7 +663,9 @@ static gp_status progset_finish(ProgData&& pd, void* stream, gp_progset** ps) {
         if ((st = core_ready(vi, s)) != GP_OK) return st;
         Workspace& w = workspace(s);
         std::lock_guard<std::mutex> g(w.mu);
-        if ((st = prepare_programs(p->pd, vi, p->dps[vi], false, 0, s, w, nullptr, nullptr)) != GP_OK) return st;
+        p->groups = base_groups(p->pd);
+        if ((st = prepare_programs(p->pd, vi, p->dps[vi], false, p->groups, s, w, nullptr, nullptr)) != GP_OK)
+            return st;
     }
     *ps = p.release();
     return GP_OK;
@@ -665,10 +714,10 @@ gp_status gp_progset_eval(gp_progset* ps, const float* X, int32_t n_feat, int64_
         // Boolean set: X and y are 32-bit words, n_cases counts bits
         if (n_cases < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
         if (n_cases > 0x7FFFFFFF) return fail(GP_E_INVAL, "n_cases above 2^31 - 1 (hit counts are int32)");
-        return eval_core(ps->pd, ps->dps, false, X, n_feat, (n_cases + 31) / 32, y, kind, out, s, w, nullptr,
+        return eval_core(ps->pd, ps->dps, false, X, n_feat, (n_cases + 31) / 32, y, kind, out, s, &w, nullptr,
                          n_cases);
     }
-    return eval_core(ps->pd, ps->dps, false, X, n_feat, n_cases, y, kind, out, s, w, nullptr);
+    return eval_core(ps->pd, ps->dps, false, X, n_feat, n_cases, y, kind, out, s, &w, nullptr);
 }
 
 gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {

@@ -121,6 +121,13 @@ struct EvalOptions {
     int32_t group_instr = 0;     // core instructions per program group, 0 = automatic
     int32_t tiles_per_wave = 0;  // tiles each wave walks per group, 0 = automatic
     int32_t target_blocks = 0;   // blocks the launch should have at least, 0 = automatic
+    // Evaluation without any allocation or upload: the programs and the group
+    // layout for `groups` groups are already on the device (a program set),
+    // and the partial sums go to `partials` (at most `partials_bytes`).
+    bool no_alloc = false;
+    int32_t groups = 0;
+    double* partials = nullptr;
+    size_t partials_bytes = 0;
 };
 
 Workspace& workspace(hipStream_t s);
@@ -141,7 +148,21 @@ int default_variant(const ProgData& pd);
 // Boolean programs (pd.opset == OPSET_BOOL) take X and y as 32-bit words, N
 // words per row, and n_bits > 0 cases; every other call passes n_bits = 0.
 gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
-                    int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace& w,
+                    int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace* w,
                     const EvalOptions* opt, int64_t n_bits = 0);
+}  // namespace gpx
+
+struct gp_progset;
+
+namespace gpx {
+// Evaluate a program set as gp_progset_eval does, with nothing allocated or
+// uploaded: the partial sums go to `partials` (device memory of
+// `partials_bytes`); the set's programs and group layout were uploaded when
+// it was created.
+gp_status progset_eval_no_alloc(gp_progset* ps, const float* X, int32_t n_feat, int64_t n_cases, const float* y,
+                                int32_t kind, void* out, hipStream_t s, double* partials, size_t partials_bytes);
+// Program groups of a launch over plentiful case tiles (the layout a program
+// set uploads when it is created).
+int32_t base_groups(const ProgData& pd);
 
 }  // namespace gpx
