@@ -20,8 +20,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "gp_oracle.c")
 LIB = os.path.join(_HERE, "liboracle.so")
 
-SUM_ABS, MSE, HITS, CASES = 0, 1, 2, 3
-_KINDS = {"sum_abs": SUM_ABS, "mse": MSE, "hits": HITS, "cases": CASES}
+SUM_ABS, MSE, HITS, CASES, CLASS_ERR = 0, 1, 2, 3, 4
+_KINDS = {"sum_abs": SUM_ABS, "mse": MSE, "hits": HITS, "cases": CASES, "class_err": CLASS_ERR}
+_INT_KINDS = (HITS, CLASS_ERR)
 
 
 def build(force: bool = True) -> str:
@@ -62,6 +63,8 @@ def lib():
         L.orc_bool_hits.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_int64, P, P]
         L.orc_apply.argtypes = [C.c_int, C.c_float, C.c_float]
         L.orc_apply.restype = C.c_float
+        L.orc_apply3.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float]
+        L.orc_apply3.restype = C.c_float
         assert L.orc_sizeof_lgp_ins() == C.sizeof(LgpIns)
         _lib = L
     return _lib
@@ -111,7 +114,7 @@ def fitness(o, y, kind):
     rc = lib().orc_fitness(_p(o), _p(y), len(o), kind_id(kind), C.byref(s), C.byref(f), C.byref(h))
     if rc != 0:
         raise ValueError("oracle: bad fitness kind")
-    return (h.value if kind_id(kind) == HITS else f.value), s.value
+    return (h.value if kind_id(kind) in _INT_KINDS else f.value), s.value
 
 
 def eval_tree(tok, cst, off, X, y, kind, nudge=0, threads=1, return_sums=False):
@@ -120,7 +123,7 @@ def eval_tree(tok, cst, off, X, y, kind, nudge=0, threads=1, return_sums=False):
     P = len(off) - 1
     k = kind_id(kind)
     y = _c(y if y is not None else np.zeros(N, np.float32), np.float32)
-    out = np.empty((P, N) if k == CASES else P, np.int32 if k == HITS else np.float32)
+    out = np.empty((P, N) if k == CASES else P, np.int32 if k in _INT_KINDS else np.float32)
     sums = np.zeros(P, np.float64)
     rc = lib().orc_eval_tree(_p(tok), _p(cst), _p(off), P, _p(X), F, N, _p(y), k, nudge,
                              threads, _p(out), _p(sums))
@@ -136,7 +139,7 @@ def eval_linear(code, off, cst, cst_off, n_reg, X, y, kind, nudge=0, threads=1, 
     P = len(off) - 1
     k = kind_id(kind)
     y = _c(y if y is not None else np.zeros(N, np.float32), np.float32)
-    out = np.empty((P, N) if k == CASES else P, np.int32 if k == HITS else np.float32)
+    out = np.empty((P, N) if k == CASES else P, np.int32 if k in _INT_KINDS else np.float32)
     sums = np.zeros(P, np.float64)
     rc = lib().orc_eval_linear(_p(code), _p(off), _p(cst), _p(cst_off), P, n_reg, _p(X), F, N,
                                _p(y), k, nudge, threads, _p(out), _p(sums))
@@ -147,6 +150,11 @@ def eval_linear(code, off, cst, cst_off, n_reg, X, y, kind, nudge=0, threads=1, 
 
 def apply(op, a, b=0.0):
     return np.float32(lib().orc_apply(op, float(np.float32(a)), float(np.float32(b))))
+
+
+def apply3(op, a, b, c):
+    """A three-operand function (IF) on one case."""
+    return np.float32(lib().orc_apply3(op, float(np.float32(a)), float(np.float32(b)), float(np.float32(c))))
 
 
 def apply_vec(op, a, b=None):

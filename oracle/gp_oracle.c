@@ -38,10 +38,22 @@
  *   expc(a)   = exp(a > 88 ? 88 : a)          (NaN passes through the compare)
  *   sin, cos, exp, log are computed in binary64 and rounded once to binary32.
  *
+ * Classification functions (section 4.2: the Shuttle and KDD Cup 99 problems
+ * add {>, <, ==, AND, OR, IF} to the arithmetic set; the paper names them
+ * without defining them).  Readings taken here: a comparison gives 1 or 0;
+ * AND, OR and IF take a value as true when it is not zero (so NaN is true);
+ * IF(a, b, c) = (a != 0) ? b : c, its three operands all evaluated.  In an
+ * arithmetic tree the opcodes 8 and 9 (AND and OR of the Boolean set) are
+ * these logical functions.
+ *
  * Fitness: d = o - y in binary32; the term is |d| (sum of absolute errors),
  * d*d (mean squared error) or the hit (o > 0) == (y > 0); sums of terms are
  * accumulated in binary64 in case order and rounded to binary32 at the end
- * (MSE divides by N first).  Hits are an exact integer count.
+ * (MSE divides by N first).  Hits are an exact integer count.  The
+ * classification fitness (Table 2: the sum of incorrect classifications)
+ * decodes the output to the class rint(o) (binary32, ties to even) and counts
+ * the cases where it differs from y, the class index; a NaN or infinite output
+ * is never a class.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared -pthread -lm
  */
@@ -53,9 +65,10 @@
 
 /* interchange-format opcodes */
 enum { O_ADD = 0, O_SUB = 1, O_MUL = 2, O_PDIV = 3, O_SIN = 4, O_COS = 5,
-       O_EXPC = 6, O_PLOG = 7, O_VAR = 64, O_CONST = 65 };
+       O_EXPC = 6, O_PLOG = 7, O_LAND = 8, O_LOR = 9, O_GT = 12, O_LT = 13,
+       O_EQ = 14, O_IF = 15, O_VAR = 64, O_CONST = 65 };
 /* fitness kinds */
-enum { K_SUM_ABS = 0, K_MSE = 1, K_HITS = 2, K_CASES = 3 };
+enum { K_SUM_ABS = 0, K_MSE = 1, K_HITS = 2, K_CASES = 3, K_CLASS = 4 };
 
 #define ORC_OK 0
 #define ORC_BAD (-1)
@@ -64,6 +77,8 @@ static int arity_of(int op)
 {
     switch (op) {
     case O_ADD: case O_SUB: case O_MUL: case O_PDIV: return 2;
+    case O_LAND: case O_LOR: case O_GT: case O_LT: case O_EQ: return 2;
+    case O_IF: return 3;
     case O_SIN: case O_COS: case O_EXPC: case O_PLOG: return 1;
     case O_VAR: case O_CONST: return 0;
     default: return -1;
@@ -109,8 +124,18 @@ static float apply_binary(int op, float a, float b)
     case O_SUB: return a - b;
     case O_MUL: return a * b;
     case O_PDIV: return (fabsf(b) < 1e-6f) ? 1.0f : a / b;
+    case O_GT: return (a > b) ? 1.0f : 0.0f;
+    case O_LT: return (a < b) ? 1.0f : 0.0f;
+    case O_EQ: return (a == b) ? 1.0f : 0.0f;
+    case O_LAND: return (a != 0.0f && b != 0.0f) ? 1.0f : 0.0f;
+    case O_LOR: return (a != 0.0f || b != 0.0f) ? 1.0f : 0.0f;
     default: return NAN;
     }
+}
+
+static float apply_ternary(int op, float a, float b, float c)
+{
+    return op == O_IF ? ((a != 0.0f) ? b : c) : NAN;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -148,6 +173,10 @@ static float eval_prefix(const int32_t* tok, const float* cst, int64_t* i,
     }
     float a = eval_prefix(tok, cst, i, X, N, c, nudge);
     float b = eval_prefix(tok, cst, i, X, N, c, nudge);
+    if (arity_of(op) == 3) {
+        float d = eval_prefix(tok, cst, i, X, N, c, nudge);
+        return apply_ternary(op, a, b, d);
+    }
     return apply_binary(op, a, b);
 }
 
@@ -191,9 +220,10 @@ int orc_fitness(const float* o, const float* y, int64_t N, int kind,
         if (kind == K_SUM_ABS) s += (double)fabsf(d);
         else if (kind == K_MSE) { float q = d * d; s += (double)q; }
         else if (kind == K_HITS) h += ((o[c] > 0.0f) == (y[c] > 0.0f));
+        else if (kind == K_CLASS) h += !(rintf(o[c]) == y[c]);
         else return ORC_BAD;
     }
-    if (sum_out) *sum_out = (kind == K_HITS) ? (double)h : s;
+    if (sum_out) *sum_out = (kind == K_HITS || kind == K_CLASS) ? (double)h : s;
     if (fit_out) {
         if (kind == K_SUM_ABS) *fit_out = (float)s;
         else if (kind == K_MSE) *fit_out = (float)(s / (double)N);
@@ -220,7 +250,7 @@ static int check_linear(const uint32_t* code, int64_t n, int64_t n_cst,
         int op = w & 0xFF, dst = (w >> 8) & 0xFF;
         int s[2] = { (int)((w >> 16) & 0xFF), (int)((w >> 24) & 0xFF) };
         int a = arity_of(op);
-        if (a < 1) return ORC_BAD;
+        if (a < 1 || a > 2) return ORC_BAD;     /* no ternary function in the register form */
         if (dst >= R) return ORC_BAD;
         for (int q = 0; q < a; q++) {
             int id = s[q];
@@ -311,7 +341,7 @@ static void* run_job(void* arg)
         double s; float f; int32_t h;
         rc = orc_fitness(o, j->y, j->N, j->kind, &s, &f, &h);
         if (rc != ORC_OK) { j->status = rc; break; }
-        if (j->kind == K_HITS) ((int32_t*)j->out)[p] = h;
+        if (j->kind == K_HITS || j->kind == K_CLASS) ((int32_t*)j->out)[p] = h;
         else ((float*)j->out)[p] = f;
         if (j->sums) j->sums[p] = s;
     }
@@ -346,7 +376,7 @@ int orc_eval_tree(const int32_t* tok, const float* cst, const int64_t* off, int3
                   const float* X, int32_t F, int64_t N, const float* y, int kind,
                   int nudge, int n_threads, void* out, double* sums)
 {
-    if (P < 0 || N < 1 || F < 1 || kind < 0 || kind > K_CASES) return ORC_BAD;
+    if (P < 0 || N < 1 || F < 1 || kind < 0 || kind > K_CLASS) return ORC_BAD;
     job_t b; memset(&b, 0, sizeof b);
     b.form = 0; b.tok = tok; b.tcst = cst; b.toff = off;
     b.X = X; b.F = F; b.N = N; b.y = y; b.kind = kind; b.nudge = nudge;
@@ -359,7 +389,7 @@ int orc_eval_linear(const uint32_t* code, const int64_t* off, const float* cst,
                     int32_t F, int64_t N, const float* y, int kind, int nudge,
                     int n_threads, void* out, double* sums)
 {
-    if (P < 0 || N < 1 || F < 1 || kind < 0 || kind > K_CASES) return ORC_BAD;
+    if (P < 0 || N < 1 || F < 1 || kind < 0 || kind > K_CLASS) return ORC_BAD;
     job_t b; memset(&b, 0, sizeof b);
     b.form = 1; b.code = code; b.loff = off; b.lcst = cst; b.lcst_off = cst_off; b.R = R;
     b.X = X; b.F = F; b.N = N; b.y = y; b.kind = kind; b.nudge = nudge;
@@ -419,12 +449,19 @@ int orc_rpn_eval(const int32_t* tok, const float* cst, int64_t n, const float* X
             if (sp < 1) return ORC_BAD;
             st[sp - 1] = apply_unary(op, st[sp - 1], 0);
             fetch += 1;
-        } else {
+        } else if (a == 2) {
             if (sp < 2) return ORC_BAD;
             float b = st[--sp];
             float x = st[sp - 1];
             st[sp - 1] = apply_binary(op, x, b);
             fetch += 2;
+        } else {
+            if (sp < 3) return ORC_BAD;
+            float d = st[--sp];
+            float b = st[--sp];
+            float x = st[sp - 1];
+            st[sp - 1] = apply_ternary(op, x, b, d);
+            fetch += 3;
         }
         if (sp > hi) hi = sp;
     }
@@ -453,7 +490,7 @@ int orc_rpn_to_lgp(const int32_t* tok, const float* cst, int64_t n, orc_lgp_ins*
     for (int64_t i = 0; i < n; i++) {
         int op = tok[i] & 0xFF;
         int a = arity_of(op);
-        if (a < 0) return ORC_BAD;
+        if (a < 0 || a > 2) return ORC_BAD;     /* the record holds at most two operands */
         if (a == 0) {
             if (sp >= 4096) return ORC_BAD;
             sk[sp] = (op == O_VAR) ? 1 : 2;
@@ -519,6 +556,11 @@ int orc_lgp_eval(const orc_lgp_ins* ins, int64_t m, const float* X, int64_t N, i
 float orc_apply(int op, float a, float b)
 {
     return arity_of(op) == 1 ? apply_unary(op, a, 0) : apply_binary(op, a, b);
+}
+
+float orc_apply3(int op, float a, float b, float c)
+{
+    return apply_ternary(op, a, b, c);
 }
 
 int orc_sizeof_lgp_ins(void) { return (int)sizeof(orc_lgp_ins); }

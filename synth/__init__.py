@@ -40,6 +40,13 @@ AND, OR, NAND, NOR = 8, 9, 10, 11
 ARITY.update({AND: 2, OR: 2, NAND: 2, NOR: 2})
 NAMES.update({AND: "and", OR: "or", NAND: "nand", NOR: "nor"})
 BOOL_SET = (AND, OR, NAND, NOR)
+# Classification functions (the Shuttle and KDD Cup 99 problems); in arithmetic
+# trees AND and OR are the logical functions.  IF is the one three-operand function.
+GT, LT, EQ, IF = 12, 13, 14, 15
+ARITY.update({GT: 2, LT: 2, EQ: 2, IF: 3})
+NAMES.update({GT: ">", LT: "<", EQ: "==", IF: "if"})
+SHUTTLE_SET = (MUL, PDIV, ADD, SUB, GT, LT, EQ, AND, OR, IF)
+KDD_SET = (ADD, SUB, MUL, PDIV, GT, LT, EQ, AND, OR, IF, SIN, COS, PLOG, EXPC)
 
 SRC_CONST_BASE = 128
 
@@ -595,3 +602,92 @@ def mux_workload(seed: int = 6, k: int = 4, n_prog: int = 4096, max_size: int = 
     pop = ptc2_population(rng, n_prog, BOOL_SET, Xw.shape[0], 1, max_size, 0.0)
     return BoolWorkload("mux%d-%dx%d" % (Xw.shape[0], n_prog, n_cases), pop, Xw, yw, n_cases,
                         dict(k=k, n_in=Xw.shape[0]))
+
+
+# ----------------------------------------------------------------------------
+# Classification (stand-ins shaped like the Shuttle and KDD Cup 99 problems)
+# ----------------------------------------------------------------------------
+@dataclass
+class ClassWorkload:
+    name: str
+    pop: TreePop
+    X: np.ndarray              # (F, N) float32
+    y: np.ndarray              # (N,) float32 class indices
+    n_classes: int
+    kind: str = "class_err"
+    meta: dict = field(default_factory=dict)
+
+
+def class_labels(rng, n_cases, probs) -> np.ndarray:
+    """Class indices drawn with the given class probabilities."""
+    p = np.asarray(probs, np.float64)
+    return rng.choice(len(p), size=n_cases, p=p / p.sum()).astype(np.int64)
+
+
+def _tail_probs(head, n_classes):
+    """The head probabilities, then the rest of the mass over the remaining
+    classes halving from one class to the next."""
+    rest = n_classes - len(head)
+    w = 0.5 ** np.arange(rest)
+    return list(head) + list((1.0 - sum(head)) * w / w.sum())
+
+
+def shuttle_cases(rng, n_cases=58000, n_feat=9, n_classes=10):
+    """Shuttle-shaped cases: 9 integer-valued inputs, 10 classes with 75 % of
+    the cases in one of them; each class has its own centre in [-100, 100]
+    per input and the inputs scatter around it with sigma 15."""
+    y = class_labels(rng, n_cases, _tail_probs([0.75], n_classes))
+    centre = rng.uniform(-100.0, 100.0, size=(n_classes, n_feat))
+    X = np.rint(centre[y].T + rng.normal(0.0, 15.0, size=(n_feat, n_cases))).astype(np.float32)
+    return np.ascontiguousarray(X), y.astype(np.float32)
+
+
+def kdd_cases(rng, n_cases=494021, n_feat=41, n_classes=22):
+    """KDD-Cup-99-shaped cases: 41 inputs, 22 classes, three of them holding
+    57 %, 22 % and 20 % of the cases.  Inputs come in four kinds by index mod
+    4: counts in 0..511, rates in [0, 1] with two decimals, heavy-tailed
+    byte counts (lognormal, up to about 1e7) and small integers in 0..10;
+    each class shifts every input's distribution its own way."""
+    y = class_labels(rng, n_cases, _tail_probs([0.568, 0.217, 0.197], n_classes))
+    shift = rng.uniform(0.0, 1.0, size=(n_classes, n_feat))
+    X = np.empty((n_feat, n_cases), np.float32)
+    for f in range(n_feat):
+        s = shift[y, f]
+        k = f % 4
+        if k == 0:
+            v = np.minimum(511, rng.poisson(1.0 + 300.0 * s))
+        elif k == 1:
+            v = np.round(np.clip(s + rng.normal(0.0, 0.1, n_cases), 0.0, 1.0), 2)
+        elif k == 2:
+            v = np.round(np.minimum(1e7, rng.lognormal(2.0 + 8.0 * s, 1.5)))
+        else:
+            v = np.minimum(10, rng.poisson(0.2 + 5.0 * s))
+        X[f] = v
+    return X, y.astype(np.float32)
+
+
+def shuttle_workload(seed: int = 7, n_prog: int = 4096, n_cases: int = 58000, max_size: int = 256) -> ClassWorkload:
+    """The Shuttle problem's shape: 58,000 cases x 9 inputs, 10 classes;
+    4096 PTC2 trees of size U{1..256} over {*, /, +, -, >, <, ==, AND, OR,
+    IF} with the 9 inputs and constants U(-200, 200) as terminals (a
+    constant with probability 1/10); fitness = incorrect classifications."""
+    rng = rng_for(seed)
+    X, y = shuttle_cases(rng, n_cases)
+    F = X.shape[0]
+    pop = ptc2_population(rng, n_prog, SHUTTLE_SET, F, 1, max_size, 1.0 / (F + 1), crange=(-200.0, 200.0))
+    return ClassWorkload("shuttle-%dx%d-F%d-C10" % (n_prog, n_cases, F), pop, X, y, 10,
+                         meta=dict(n_feat=F, n_classes=10))
+
+
+def kdd_workload(seed: int = 8, n_prog: int = 4096, n_cases: int = 494021, max_size: int = 256) -> ClassWorkload:
+    """The KDD Cup 99 problem's shape: 494,021 cases x 41 inputs, 22 classes;
+    4096 PTC2 trees of size U{1..256} over {+, -, *, /, >, <, ==, AND, OR,
+    IF, sin, cos, log, exp} with the 41 inputs and constants U(-20000,
+    20000) as terminals (a constant with probability 1/42); fitness =
+    incorrect classifications."""
+    rng = rng_for(seed)
+    X, y = kdd_cases(rng, n_cases)
+    F = X.shape[0]
+    pop = ptc2_population(rng, n_prog, KDD_SET, F, 1, max_size, 1.0 / (F + 1), crange=(-20000.0, 20000.0))
+    return ClassWorkload("kdd-%dx%d-F%d-C22" % (n_prog, n_cases, F), pop, X, y, 22,
+                         meta=dict(n_feat=F, n_classes=22))

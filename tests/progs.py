@@ -4,7 +4,8 @@ import numpy as np
 import synth
 
 _OPS = {"+": synth.ADD, "-": synth.SUB, "*": synth.MUL, "/": synth.PDIV,
-        "sin": synth.SIN, "cos": synth.COS, "exp": synth.EXPC, "log": synth.PLOG}
+        "sin": synth.SIN, "cos": synth.COS, "exp": synth.EXPC, "log": synth.PLOG,
+        ">": synth.GT, "<": synth.LT, "==": synth.EQ, "and": synth.AND, "or": synth.OR, "if": synth.IF}
 
 
 def _lex(s):

@@ -363,3 +363,103 @@ def test_malformed_rejected():
     with pytest.raises(ValueError):
         oracle.tree_outputs(np.array([synth.var_tok(5)], np.int32), np.zeros(1, np.float32),
                             np.array([0, 1]), np.zeros((1, 4), np.float32))
+
+
+# --------------------------------------------------------------------------
+# Classification functions (section 4.2: >, <, ==, AND, OR, IF) and the
+# classification fitness (Table 2: the sum of incorrect classifications)
+# --------------------------------------------------------------------------
+NAN = float("nan")
+
+
+@pytest.mark.parametrize("op,cases", [
+    (synth.GT, [(2, 1, 1), (1, 2, 0), (1, 1, 0), (-0.0, 0.0, 0), (NAN, 0, 0), (0, NAN, 0), (math.inf, 1e38, 1)]),
+    (synth.LT, [(2, 1, 0), (1, 2, 1), (1, 1, 0), (-math.inf, -1e38, 1), (NAN, 1, 0)]),
+    (synth.EQ, [(1, 1, 1), (1, 2, 0), (0.0, -0.0, 1), (NAN, NAN, 0), (math.inf, math.inf, 1)]),
+    (synth.AND, [(0, 0, 0), (0, 5, 0), (3, 0, 0), (2, -7, 1), (-0.0, 1, 0), (NAN, 1, 1), (1e-45, 1, 1)]),
+    (synth.OR, [(0, 0, 0), (0, 5, 1), (3, 0, 1), (-0.0, 0.0, 0), (NAN, 0, 1), (0, -1e-45, 1)]),
+])
+def test_classification_functions_truth_tables(op, cases):
+    """Comparisons give 1 or 0 (false whenever a NaN is involved, IEEE);
+    AND / OR treat every non-zero value, NaN included, as true."""
+    for a, b, want in cases:
+        got = oracle.apply(op, a, b)
+        assert got == f32(want) and not math.copysign(1.0, got) < 0, (op, a, b, got)
+
+
+def test_if_selects_on_non_zero():
+    for a, want in [(0.0, "c"), (-0.0, "c"), (1.0, "b"), (-2.5, "b"), (NAN, "b"), (1e-45, "b"), (math.inf, "b")]:
+        got = oracle.apply3(synth.IF, a, 7.0, -3.0)
+        assert got == (f32(7) if want == "b" else f32(-3)), (a, got)
+    # the selected operand is returned unchanged, signed zeros and NaN included
+    assert math.copysign(1.0, oracle.apply3(synth.IF, 1.0, -0.0, 5.0)) < 0
+    assert math.isnan(oracle.apply3(synth.IF, 0.0, 1.0, NAN))
+
+
+def test_classification_trees_closed_forms():
+    """IF over comparisons builds max and |x| (nonzero, distinct inputs, so
+    signed zeros and ties do not arise); AND/OR of comparisons build
+    interval tests, checked against numpy's float32 comparisons."""
+    rng = synth.rng_for(71)
+    a = rng.uniform(-5, 5, 2000).astype(np.float32)
+    b = rng.uniform(-5, 5, 2000).astype(np.float32)
+    keep = (a != b) & (a != 0) & (b != 0)
+    X = np.stack([a[keep], b[keep]])
+    assert np.array_equal(one("(if (> x0 x1) x0 x1)", X)[0], np.maximum(X[0], X[1]))
+    assert np.array_equal(one("(if (< x0 x1) x0 x1)", X)[0], np.minimum(X[0], X[1]))
+    assert np.array_equal(one("(if (< x0 0) (- 0 x0) x0)", X)[0], np.abs(X[0]))
+    inside = ((X[0] > -1) & (X[0] < 2)).astype(np.float32)
+    assert np.array_equal(one("(and (> x0 -1) (< x0 2))", X)[0], inside)
+    outside = ((X[0] < -1) | (X[0] > 2)).astype(np.float32)
+    assert np.array_equal(one("(or (< x0 -1) (> x0 2))", X)[0], outside)
+    # x == x is 1 for every non-NaN x, and IF with equal branches is the branch
+    assert np.all(one("(== x0 x0)", X)[0] == 1)
+    assert np.array_equal(one("(if x0 x1 x1)", X)[0], X[1])
+
+
+def test_class_fitness_closed_forms():
+    """Decoding is rint (ties to even) and the fitness counts mismatches."""
+    rng = synth.rng_for(72)
+    X = rng.uniform(-3, 3, (1, 1000)).astype(np.float32)
+    y = (X[0] > 0).astype(np.float32)           # class 1 where x0 > 0, else 0
+    p = progs.pop("(if (> x0 0) 1 0)", "(if (> x0 0) 0 1)", "(> x0 0)", "0.4", "-0.4", "0.6")
+    got = oracle.eval_tree(p.tok, p.cst, p.off, X, y, "class_err")
+    n1 = int(y.sum())
+    assert got.dtype == np.int32
+    assert list(got) == [0, 1000, 0, n1, n1, 1000 - n1]
+    ties = progs.pop("2.5", "3.5", "-0.5", "1e30")
+    yy = np.array([2.0, 4.0, 0.0, 1e30], np.float32)
+    for k in range(4):
+        g = oracle.eval_tree(ties.tok, ties.cst, ties.off, X[:, :4], np.full(4, yy[k], np.float32), "class_err")
+        assert g[k] == 0, (k, g)
+    nan = progs.pop("(/ (- x0 x0) (* 0 x0))", "(log 0)")   # 0 / 0 is protected: 1; log 0 -> 0
+    g = oracle.eval_tree(nan.tok, nan.cst, nan.off, X, np.ones(1000, np.float32), "class_err")
+    assert list(g) == [0, 1000]
+
+
+def test_classification_recursive_and_rpn_agree():
+    """The recursive interpreter and the one-dimensional-stack RPN
+    interpreter evaluate trees with IF to the same bits."""
+    rng = synth.rng_for(73)
+    pop = synth.ptc2_population(rng, 60, synth.SHUTTLE_SET, 3, 1, 60, 0.25, crange=(-2.0, 2.0))
+    X = synth.uniform_cases(rng, 3, 25, -2, 2)
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    assert np.any((pop.tok & 0xFF) == synth.IF)
+    for p in range(pop.n_prog):
+        t, c = pop.program(p)
+        rt, rc = oracle.prefix_to_rpn(t, c)
+        for cc in range(X.shape[1]):
+            v, _, _ = oracle.rpn_eval(rt, rc, X, cc)
+            assert v.view(np.int32) == ref[p, cc].view(np.int32) or (np.isnan(v) and np.isnan(ref[p, cc]))
+
+
+def test_register_form_takes_binary_classification_functions_only():
+    rng = synth.rng_for(74)
+    X = synth.uniform_cases(rng, 2, 50, -2, 2)
+    code = np.array([synth.lin_word(synth.GT, 0, 2, 3), synth.lin_word(synth.AND, 0, 0, 1)], np.uint32)
+    out = oracle.linear_outputs(code, np.array([0, 2]), np.zeros(0, np.float32), np.array([0, 0]), 2, X)
+    # r1 starts as x1: r0 = (x0 > x1) AND x1
+    assert np.array_equal(out[0], ((X[0] > X[1]) & (X[1] != 0)).astype(np.float32))
+    bad = np.array([synth.lin_word(synth.IF, 0, 2, 3)], np.uint32)
+    with pytest.raises(ValueError):
+        oracle.linear_outputs(bad, np.array([0, 1]), np.zeros(0, np.float32), np.array([0, 0]), 2, X)
