@@ -14,6 +14,11 @@ Workloads (synthetic, seeded):
   linear       4096 register programs of 32-256 instructions, 8 registers,
                16 features x 1,048,576 cases ~N(0,1), hit count
   tiny-tree    100 ramped half-and-half trees, 1024 cases, sum |error|
+  shuttle      4096 PTC2 trees of 1-256 nodes over {*,/,+,-,>,<,==,AND,OR,IF},
+               58,000 Shuttle-shaped cases x 9 inputs, 10 classes, incorrect
+               classifications
+  kdd          the same over {+,-,*,/,>,<,==,AND,OR,IF,sin,cos,log,exp},
+               494,021 KDD-Cup-99-shaped cases x 41 inputs, 22 classes
   batched      10,000 programs in 40 populations (trees and register programs,
                lognormal lengths 8-1024) over three resident case matrices of
                4096 / 65536 / 1,048,576 cases x 8 features, one autotuned
@@ -73,6 +78,10 @@ def make_workload(name):
         return synth.tiny_tree_workload()
     if name == "linear":
         return synth.linear_workload()
+    if name == "shuttle":
+        return synth.shuttle_workload()
+    if name == "kdd":
+        return synth.kdd_workload()
     raise SystemExit("unknown workload " + name)
 
 
@@ -93,6 +102,7 @@ def gpu_targets(target, X, noise):
 
 
 def host_cores():
+    """Threads the oracle may use: the CPUs this process may run on (at most 16)."""
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -100,34 +110,51 @@ def host_cores():
     return max(1, min(cores, 16))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, y_host, budget_s=10.0):
-    """The oracle as it stands, on the host cores, on a bounded sample of
-    the same workload: evenly spaced programs over all cases."""
+    """The oracle as it stands, on a bounded sample of the same workload
+    (evenly spaced programs over all cases): on all the host cores it may use
+    (`value`, `cores`) and on one core (`single_thread`)."""
     import oracle
-    cores = host_cores()
-    tree = hasattr(w, "target")
+    tree = hasattr(w.pop, "tok")
     P = w.pop.n_prog
     N = w.X.shape[1]
 
-    def run(idx):
+    def run(idx, threads):
         sub = w.pop.subset(idx)
         t0 = time.perf_counter()
         if tree:
-            oracle.eval_tree(sub.tok, sub.cst, sub.off, w.X, y_host, w.kind, threads=cores)
+            oracle.eval_tree(sub.tok, sub.cst, sub.off, w.X, y_host, w.kind, threads=threads)
         else:
             oracle.eval_linear(sub.code, sub.off, sub.cst, sub.cst_off, sub.n_reg, w.X, y_host, w.kind,
-                               threads=cores)
+                               threads=threads)
         return int(np.sum(sub.sizes())) * N, time.perf_counter() - t0
 
-    probe = np.linspace(0, P - 1, min(P, 2 * cores)).astype(int)
-    ops, dt = run(probe)
-    want_ops = ops / max(dt, 1e-9) * budget_s
-    n = int(min(P, max(len(probe), want_ops / max(ops / len(probe), 1))))
-    idx = np.linspace(0, P - 1, n).astype(int)
-    ops, dt = run(idx)
-    return {"value": ops / dt, "unit": "GPop/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d programs (evenly spaced) x all %d cases, %.3g GPop in %.1f s"
-                      % (n, P, N, ops, dt)}
+    def timed(threads, budget):
+        probe = np.linspace(0, P - 1, min(P, 2 * threads)).astype(int)
+        ops, dt = run(probe, threads)
+        want_ops = ops / max(dt, 1e-9) * budget
+        n = int(min(P, max(len(probe), want_ops / max(ops / len(probe), 1))))
+        idx = np.linspace(0, P - 1, n).astype(int)
+        ops, dt = run(idx, threads)
+        return ops / dt, "%d of %d programs (evenly spaced) x all %d cases, %.3g GPop in %.1f s" % (n, P, N, ops, dt)
+
+    cores = host_cores()
+    v_all, s_all = timed(cores, budget_s)
+    v_one, s_one = timed(1, budget_s / 2)
+    return {"value": v_all, "unit": "GPop/s", "cores": cores, "kind": "oracle", "sample": s_all,
+            "single_thread": {"value": v_one, "unit": "GPop/s", "cores": 1, "sample": s_one},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def traffic_record(workload, kernel):
@@ -145,6 +172,43 @@ def traffic_record(workload, kernel):
                 if kv.get("workload") == workload and kv.get("kernel") == kernel and kv.get("source") == digest:
                     return int(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
+
+
+def counter_record(workload, kernel, tag="valu-record"):
+    """Instruction counts per launch of `kernel` on `workload` from a committed
+    counter summary measured with the kernel's current sources, else None."""
+    import paper_1601_00221_amd as gp
+    digest = gp.kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                line = line.strip().strip("`")
+                if not line.startswith(tag + ":"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
+                if kv.get("workload") == workload and kv.get("kernel") == kernel and kv.get("source") == digest:
+                    return kv, os.path.relpath(path, ROOT)
+    return None, None
+
+
+# vector ALU issue rate of the chip: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def op_mix_ceiling(gpop_per_launch, launch_s, kernel, workload):
+    """The GPop/s this kernel would reach on this workload if its vector ALUs
+    issued on every cycle: GP operations per launch over the time its own
+    measured vector instructions take at the full issue rate (their count per
+    launch from the committed counter summary of the current sources), and
+    the measured rate as a fraction of it."""
+    kv, src = counter_record(workload, kernel)
+    if kv is None:
+        return None
+    valu = float(kv["valu_insts"])
+    ceil = gpop_per_launch / (valu / VALU_WAVE_INSTS_PER_S)
+    achieved = gpop_per_launch / launch_s
+    return {"gpops": ceil, "frac": achieved / ceil, "valu_insts_per_launch": valu,
+            "gpop_per_valu_lane_op": gpop_per_launch / (valu * 64), "source": src}
 
 
 def roofline(gpop_per_launch, launch_s, kernel, workload):
@@ -186,17 +250,24 @@ def kernel_name(vi):
 # ----------------------------------------------------------------------------
 # one population on one case matrix
 # ----------------------------------------------------------------------------
-def bench_single(args):
+UNPACKED_CEILING_NOTE = ("this path runs unpacked FP32 (packed FP32 is switched off in every build) with terminals "
+                         "folded into operands: on {+,-,*} trees it performs about 1.54 GP operations per "
+                         "vector lane-operation, so its own ceiling is 39.3 T lane-op/s x 1.54 = 61 T GPop/s")
+UNPACKED_CEILING_T = 61.0
+
+
+def time_population(args, w, steps, warmup):
+    """Evaluate a resident population on resident data: warm-up, then `steps`
+    timed steps; per-step times from events on the launch stream, the
+    evaluation kernel's mean time from the library's own events."""
     import torch
     import paper_1601_00221_amd as gp
-
-    w = make_workload(args.workload)
     N = w.X.shape[1]
     P = w.pop.n_prog
     Xd = torch.from_numpy(w.X).cuda()
-    tree = hasattr(w, "target")
+    tree = hasattr(w.pop, "tok")
     if tree:
-        yd = gpu_targets(w.target, Xd, w.noise)
+        yd = gpu_targets(w.target, Xd, w.noise) if hasattr(w, "target") else torch.from_numpy(w.y).cuda()
         ps = gp.ProgSet.tree(w.pop.tok, w.pop.cst, w.pop.off, w.X.shape[0])
     else:
         yd = torch.from_numpy(w.y).cuda()
@@ -204,23 +275,43 @@ def bench_single(args):
     info = ps.info()
     gpop_per_step = info["n_gpop"] * N
     out = gp.out_tensor(w.kind, P, N)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         ps.eval(Xd, yd, w.kind, out)
     torch.cuda.synchronize()
     gp.timing_read(reset=True)
     gp.timing_enable(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for k in range(steps):
         ps.eval(Xd, yd, w.kind, out)
+        ev[k + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     gp.timing_enable(False)
     n_launch, kernel_ms = gp.timing_read(reset=True)
-    step_s = (t1 - t0) / args.steps
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return dict(ps=ps, Xd=Xd, yd=yd, out=out, info=info, gpop_per_step=gpop_per_step,
+                step_s=(t1 - t0) / steps, kern_s=kernel_ms / 1e3 / max(n_launch, 1),
+                step_ms_median=float(np.median(step_ms)), step_ms_p10=float(np.percentile(step_ms, 10)),
+                step_ms_p90=float(np.percentile(step_ms, 90)))
+
+
+def bench_single(args):
+    import torch
+    import paper_1601_00221_amd as gp
+
+    w = make_workload(args.workload)
+    N = w.X.shape[1]
+    P = w.pop.n_prog
+    tree = hasattr(w.pop, "tok")
+    m = time_population(args, w, args.steps, args.warmup)
+    ps, Xd, yd, out, info = m["ps"], m["Xd"], m["yd"], m["out"], m["info"]
+    gpop_per_step, step_s, kern_s = m["gpop_per_step"], m["step_s"], m["kern_s"]
     value = gpop_per_step / step_s
-    kern_s = kernel_ms / 1e3 / max(n_launch, 1)
-    log("step %.3f ms, kernel %.3f ms, %.3f T GPop/s" % (step_s * 1e3, kern_s * 1e3, value / 1e12))
+    log("step %.3f ms (median %.3f, p10 %.3f, p90 %.3f), kernel %.3f ms, %.3f T GPop/s"
+        % (step_s * 1e3, m["step_ms_median"], m["step_ms_p10"], m["step_ms_p90"], kern_s * 1e3, value / 1e12))
 
     # the same evaluation through the one-shot call: host lowering + PCIe upload included
     torch.cuda.synchronize()
@@ -237,12 +328,34 @@ def bench_single(args):
     config = {"workload": w.name, "n_prog": P, "n_cases": N, "n_feat": int(w.X.shape[0]),
               "fitness": w.kind, "gpop_per_step": gpop_per_step}
     res = base_result(args, value, step_s, config)
-    res["roofline"] = roofline(gpop_per_step, kern_s, kernel_name(info["variant"]), w.name)
+    res["step_ms"] = {"median": m["step_ms_median"], "p10": m["step_ms_p10"], "p90": m["step_ms_p90"],
+                      "mean": step_s * 1e3, "steps": args.steps}
+    kname = kernel_name(info["variant"])
+    res["roofline"] = roofline(gpop_per_step, kern_s, kname, w.name)
+    res["op_mix_ceiling"] = op_mix_ceiling(gpop_per_step, kern_s, kname, w.name)
     res["call_gpops_per_s"] = gpop_per_step / call_s
+    ps.close()
+    if args.workload == "scale-tree" and not args.no_arith:
+        # the same tree shapes over {+,-,*}: the workload on which the 40 % reading is claimed
+        wa = make_workload("arith-tree")
+        ma = time_population(args, wa, args.steps, args.warmup)
+        ka = kernel_name(ma["info"]["variant"])
+        va = ma["gpop_per_step"] / ma["step_s"]
+        log("arith-tree: step %.3f ms, kernel %.3f ms, %.3f T GPop/s" % (ma["step_s"] * 1e3, ma["kern_s"] * 1e3,
+                                                                       va / 1e12))
+        ra = roofline(ma["gpop_per_step"], ma["kern_s"], ka, wa.name)
+        ra["frac_of_unpacked_ceiling"] = ma["gpop_per_step"] / ma["kern_s"] / (UNPACKED_CEILING_T * 1e12)
+        ra["unpacked_ceiling_tgpops"] = UNPACKED_CEILING_T
+        ra["unpacked_ceiling_note"] = UNPACKED_CEILING_NOTE
+        res["arith"] = {"workload": wa.name, "value": va, "unit": "GPop/s", "ms_per_step": ma["step_s"] * 1e3,
+                        "step_ms": {"median": ma["step_ms_median"], "p10": ma["step_ms_p10"],
+                                    "p90": ma["step_ms_p90"]},
+                        "pct_vector_fp32_peak": 100.0 * va / (PEAK_FP32_T * 1e12), "roofline": ra,
+                        "op_mix_ceiling": op_mix_ceiling(ma["gpop_per_step"], ma["kern_s"], ka, wa.name)}
+        ma["ps"].close()
     if not args.no_cpu:
         log("cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline(w, yd.cpu().numpy(), args.cpu_budget)
-    ps.close()
     return res
 
 
@@ -555,7 +668,7 @@ def bench_mux20(args):
 # ----------------------------------------------------------------------------
 # whole GP runs (evaluation plus breeding), as the paper measures GPop/s
 # ----------------------------------------------------------------------------
-PAPER_RUN_GPOPS = {"sextic": 53.193e9, "mux20": 1411.185e9}   # best of Table 10 (GTX 670)
+PAPER_RUN_GPOPS = {"sextic": 53.193e9, "mux20": 1411.185e9, "shuttle": 55.734e9}   # best of Table 10 (GTX 670)
 
 
 def bench_gp_run(args):
@@ -584,6 +697,14 @@ def bench_gp_run(args):
     log("20-multiplexer run ...")
     rb = gp.evolve(gp.evolve_config(synth.BOOL_SET, kind="hits", seed=12), Xb, yb, n_cases=n)
     runs["mux20-1000x50"] = rb
+    # the Shuttle-shaped classification problem: 58,000 cases x 9 inputs, constants in [-200, 200]
+    ws = synth.shuttle_workload(n_prog=1)
+    Xs = torch.from_numpy(ws.X).cuda()
+    ys = torch.from_numpy(ws.y).cuda()
+    log("shuttle-shaped run ...")
+    rs = gp.evolve(gp.evolve_config(synth.SHUTTLE_SET, kind="class_err", p_const=0.1, const_range=(-200.0, 200.0),
+                                    seed=13), Xs, ys)
+    runs["shuttle-1000x50-N58000"] = rs
     out = {}
     for name, v in runs.items():
         out[name] = {"gpops_whole_run": v["gp_ops"] / v["total_seconds"],
@@ -591,7 +712,7 @@ def bench_gp_run(args):
                      "gp_ops": v["gp_ops"], "total_s": v["total_seconds"], "eval_s": v["eval_seconds"],
                      "breed_s": v["breed_seconds"], "best_fitness": v["best_fitness"],
                      "best_generation": v["best_generation"], "best_size": v["best_size"],
-                     "paper_gpops": PAPER_RUN_GPOPS["sextic" if name.startswith("sextic") else "mux20"]}
+                     "paper_gpops": PAPER_RUN_GPOPS[name.split("-")[0]]}
         log("%s: %.3f s, %.1f G GPop/s whole run, %.1f G GPop/s evaluation, best %.4g" % (
             name, v["total_seconds"], out[name]["gpops_whole_run"] / 1e9, out[name]["gpops_evaluation"] / 1e9,
             v["best_fitness"]))
@@ -623,6 +744,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale-tree")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-arith", action="store_true", help="scale-tree: skip the {+,-,*} sub-measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--requests", type=int, default=10, help="served: requests per run")
     args = ap.parse_args()

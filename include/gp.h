@@ -41,6 +41,10 @@
  *     number of cases with (out > 0) == (y > 0) (Table 2: mean squared error
  *     for regression, a count of classifications for classification).  Sums
  *     are accumulated in binary64 and rounded to binary32 once.
+ *     GP_FIT_CLASS_ERR (Table 2: the sum of incorrect classifications) decodes
+ *     each output to the class rint(out) (binary32, ties to even) and counts
+ *     the cases where it differs from y, which holds class indices; a NaN or
+ *     infinite output is never a class.  out is int32[n_prog], like hits.
  */
 #ifndef GP_H_
 #define GP_H_
@@ -67,16 +71,28 @@ typedef enum {
     GP_FIT_SUM_ABS = 0,
     GP_FIT_MSE = 1,
     GP_FIT_HITS = 2,
-    GP_OUT_CASES = 3
+    GP_OUT_CASES = 3,
+    GP_FIT_CLASS_ERR = 4   /* classification: the number of cases whose decoded class differs from y */
 } gp_fitness_kind;
 
 /* Opcodes.  Tree token: low 8 bits = opcode, high 24 bits = feature index
- * for GP_VAR.  Linear word: op | dst << 8 | src1 << 16 | src2 << 24. */
+ * for GP_VAR.  Linear word: op | dst << 8 | src1 << 16 | src2 << 24.
+ *
+ * The classification problems of section 4.2 (Shuttle, KDD Cup 99) add
+ * {>, <, ==, AND, OR, IF} to the arithmetic functions.  The paper names them
+ * only; the definitions here are: GP_GT, GP_LT, GP_EQ give 1.0f or 0.0f (a
+ * NaN operand gives 0); in arithmetic trees GP_AND and GP_OR are the logical
+ * functions, true (1.0f) when both / either operand is non-zero (NaN counts
+ * as non-zero); GP_IF(a, b, c) = a != 0 ? b : c, the only three-operand
+ * function (trees only: register programs reject it).  gp_eval_bool reads
+ * GP_AND .. GP_NOR as bitwise functions of packed cases. */
 enum {
     GP_ADD = 0, GP_SUB = 1, GP_MUL = 2, GP_PDIV = 3,
     GP_SIN = 4, GP_COS = 5, GP_EXPC = 6, GP_PLOG = 7,
-    /* Boolean functions, for gp_eval_bool only (bitwise on 32 packed cases) */
+    /* Boolean functions (bitwise on 32 packed cases in gp_eval_bool; logical in arithmetic trees) */
     GP_AND = 8, GP_OR = 9, GP_NAND = 10, GP_NOR = 11,
+    /* classification functions */
+    GP_GT = 12, GP_LT = 13, GP_EQ = 14, GP_IF = 15,
     GP_VAR = 64, GP_CONST = 65
 };
 
@@ -84,7 +100,7 @@ enum {
  * [GP_SRC_CONST, 256) the program's constants. */
 #define GP_SRC_CONST 128
 #define GP_MAX_REG 8          /* registers of a linear program */
-#define GP_MAX_FEAT 32        /* features per case matrix */
+#define GP_MAX_FEAT 44        /* features a program may read (the KDD Cup 99 shape has 41) */
 #define GP_MAX_DEPTH 12       /* stack levels of a lowered tree */
 #define GP_MAX_LEN 65536      /* instructions (tree nodes) per program */
 
@@ -125,6 +141,8 @@ gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* 
  *              gp_eval_tree also uses (section 5, Table 7).
  * Limits: at most GP_1D_MAX_LEN instructions per program (the program must
  * fit in LDS) and GP_1D_MAX_STACK stack values; GP_E_DEPTH beyond them.
+ * Functions: the arithmetic and transcendental set (the paper's regression
+ * problem); the classification functions give GP_E_INVAL.
  * kind GP_OUT_CASES writes the per-case outputs.  Meant for measurement;
  * gp_eval_tree is the evaluator. */
 enum { GP_1D_RPN = 0, GP_1D_LGP = 1 };
@@ -172,12 +190,13 @@ typedef struct {
     int32_t init_min_depth;    /* ramped half-and-half range, e.g. 2 .. 6 */
     int32_t init_max_depth;
     int32_t mutation_depth;    /* depth limit of a mutation's new subtree, e.g. 4 */
-    uint32_t functions;        /* bit k set: opcode k (GP_ADD .. GP_NOR) is in the function set; all
-                                  arithmetic or all Boolean */
+    uint32_t functions;        /* bit k set: opcode k (GP_ADD .. GP_IF) is in the function set; the
+                                  Boolean set is GP_AND .. GP_NOR alone, an arithmetic set may add
+                                  the classification functions (GP_AND, GP_OR logical) */
     float p_const;             /* probability that a terminal is a constant (arithmetic sets) */
     float const_lo, const_hi;  /* constants uniform in [const_lo, const_hi) */
-    int32_t kind;              /* GP_FIT_MSE or GP_FIT_SUM_ABS (minimised) or GP_FIT_HITS (maximised;
-                                  the only kind for Boolean sets) */
+    int32_t kind;              /* GP_FIT_MSE, GP_FIT_SUM_ABS or GP_FIT_CLASS_ERR (minimised) or
+                                  GP_FIT_HITS (maximised; the only kind for Boolean sets) */
     uint64_t seed;             /* SplitMix64 seed: a run is reproducible from it */
 } gp_evolve_config;
 
@@ -448,8 +467,10 @@ gp_status gp_timing_read(int64_t* launches, double* total_ms, int reset);
  * for), GP2D_CODE_PREFETCH=n (scalar loads in flight, 1-15, when each
  * program's code is burst-loaded into the scalar cache; 15 by default, 0
  * for no burst load), GP2D_SAME_GROUP=1 (the four waves of a block run one program
- * group on four chunks of tiles instead of four groups on one chunk).  They
- * change the schedule only; fitness values never depend on them. */
+ * group on four chunks of tiles instead of four groups on one chunk),
+ * GP2D_VARIANT=i+1 (kernel variant i of gp_variant_info, when it can hold the
+ * programs).  They change the schedule only; fitness values never depend on
+ * them. */
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* gp_last_error(void);

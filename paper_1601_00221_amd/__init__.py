@@ -20,8 +20,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "gp.h")
 
 GP_OK, GP_E_INVAL, GP_E_NOMEM, GP_E_DEPTH, GP_E_DEVICE, GP_E_AGAIN, GP_E_NOTFOUND, GP_E_TIMEOUT = \
     0, -1, -2, -3, -4, -5, -6, -7
-GP_FIT_SUM_ABS, GP_FIT_MSE, GP_FIT_HITS, GP_OUT_CASES = 0, 1, 2, 3
-KINDS = {"sum_abs": 0, "mse": 1, "hits": 2, "cases": 3}
+GP_FIT_SUM_ABS, GP_FIT_MSE, GP_FIT_HITS, GP_OUT_CASES, GP_FIT_CLASS_ERR = 0, 1, 2, 3, 4
+KINDS = {"sum_abs": 0, "mse": 1, "hits": 2, "cases": 3, "class_err": 4}
 STATUS_NAMES = {0: "GP_OK", -1: "GP_E_INVAL", -2: "GP_E_NOMEM", -3: "GP_E_DEPTH",
                 -4: "GP_E_DEVICE", -5: "GP_E_AGAIN", -6: "GP_E_NOTFOUND", -7: "GP_E_TIMEOUT"}
 
@@ -454,7 +454,7 @@ def variants():
         t, d, f, v, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(L.gp_variant_info(i, C.byref(t), C.byref(d), C.byref(f), C.byref(v), C.byref(fl)))
         arith, boolean, trees = bool(fl.value & 1), bool(fl.value & 2), bool(fl.value & 4)
-        suffix = "_b" if boolean else ("_at" if trees else ("_a" if arith else ""))
+        suffix = "_b" if boolean else (("_at" if arith else "_t") if trees else ("_a" if arith else ""))
         out.append({"t": t.value, "depth": d.value, "n_feat": f.value, "vgprs": v.value, "no_transc": arith,
                     "boolean": boolean, "trees_only": trees,
                     "kernel": "k_core_%d_%d_%d_%d%s" % (t.value, d.value, f.value, v.value, suffix)})
@@ -550,7 +550,7 @@ def core_lower(pop, n_feat, variant, table_base):
 def out_tensor(kind, n_prog, n_cases, device="cuda"):
     import torch
     k = kind_id(kind)
-    if k == GP_FIT_HITS:
+    if k in (GP_FIT_HITS, GP_FIT_CLASS_ERR):
         return torch.empty(n_prog, dtype=torch.int32, device=device)
     if k == GP_OUT_CASES:
         return torch.empty((n_prog, n_cases), dtype=torch.float32, device=device)

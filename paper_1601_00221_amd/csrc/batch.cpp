@@ -414,8 +414,9 @@ gp_status check_datasets(const gp_dataset* ds, int32_t n_ds) {
 
 gp_status build_job(const gp_job& j, const gp_dataset* ds, int32_t n_ds, ProgData& pd) {
     if (j.dataset < 0 || j.dataset >= n_ds) return fail(GP_E_NOTFOUND, "dataset %d does not exist", j.dataset);
-    if (j.kind != GP_FIT_SUM_ABS && j.kind != GP_FIT_MSE && j.kind != GP_FIT_HITS)
-        return fail(GP_E_INVAL, "batched jobs take GP_FIT_SUM_ABS, GP_FIT_MSE or GP_FIT_HITS (got %d)", j.kind);
+    if (j.kind != GP_FIT_SUM_ABS && j.kind != GP_FIT_MSE && j.kind != GP_FIT_HITS && j.kind != GP_FIT_CLASS_ERR)
+        return fail(GP_E_INVAL, "batched jobs take GP_FIT_SUM_ABS, GP_FIT_MSE, GP_FIT_HITS or GP_FIT_CLASS_ERR (got %d)",
+                    j.kind);
     if (!j.out && j.n_prog > 0) return fail(GP_E_INVAL, "job output is null");
     if (!ds[j.dataset].y) return fail(GP_E_INVAL, "dataset %d has no targets", j.dataset);
     const int32_t F = ds[j.dataset].n_feat;

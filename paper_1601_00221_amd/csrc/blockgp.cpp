@@ -80,6 +80,14 @@ extern "C" gp_status gp_eval_tree_1d(const int32_t* tok, const float* cst, const
     ProgData pd;
     gp_status st = build_tree(tok, cst, off, n_prog, n_feat, pd);   // validates and lowers
     if (st != GP_OK || n_prog == 0) return st;
+    // the comparator reproduces the paper's regression measurements: the arithmetic and
+    // transcendental functions only
+    for (int64_t i = 0; i < off[n_prog]; i++) {
+        const int op = tok[i] & 0xFF;
+        if (op >= GP_AND && op <= GP_IF)
+            return fail(GP_E_INVAL, "token %lld: the 1D comparator runs {+,-,*,/,sin,cos,exp,log} trees only",
+                        (long long)i);
+    }
     if (!X) return fail(GP_E_INVAL, "X is null");
     if (!out) return fail(GP_E_INVAL, "out is null");
     if (n_cases < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");

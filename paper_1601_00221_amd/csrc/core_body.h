@@ -22,9 +22,15 @@
 // shared the launch.
 //
 // Kernel modes: 0 with the sin/cos/exp/log code, 1 without it (arithmetic
-// programs), 3 like 1 for trees only, 2 the Boolean function set, whose slots are 32-bit words of
-// bit-packed cases (32 cases per slot; a 256-slot block holds 8192 cases)
-// and whose fitness is the number of output bits equal to the target bits.
+// programs), 3 like 1 for trees only, 4 like 0 for trees only, 2 the Boolean
+// function set, whose slots are 32-bit words of bit-packed cases (32 cases
+// per slot; a 256-slot block holds 8192 cases) and whose fitness is the
+// number of output bits equal to the target bits.
+//
+// The classification functions (>, <, ==, logical AND and OR, IF; section
+// 4.2) are exits in every arithmetic kernel; the classification fitness
+// decodes an output to the class rint(o) and counts the cases whose class
+// differs from y.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,19 +48,56 @@ __device__ __forceinline__ float pdiv(float a, float b) { return (fabsf(b) < 1e-
 
 // Exit payload: byte 0 offset of A, byte 1 offset of B, byte 2 offset of the
 // destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
-// the constant, bit 5: B is the constant).
+// the constant, bit 5: B is the constant).  IF has a third operand: byte 2
+// is its offset, and the result goes to the lowest of the three offsets.
 template <int T, int V0, bool AR>
 __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits, const double* tab) {
     const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
     const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
     // an operand is the instruction's constant (flag set) or T slots of the
     // core's range; one scalar branch inside the helper picks
-    if (op == GP_PDIV) {
+    if (op == OP_IF) {
+        float A[T], B[T], C[T];
+        core_gather<T, V0>(oa, A);
+        core_gather<T, V0>(ob, B);
+        core_gather<T, V0>(od, C);
+#pragma unroll
+        for (int j = 0; j < T; j++) A[j] = (A[j] != 0.0f) ? B[j] : C[j];
+        const uint32_t lo = oa < ob ? oa : ob;
+        core_scatter<T, V0>(__builtin_amdgcn_readfirstlane(lo < od ? lo : od), A);   // uniform: an SGPR
+        return;
+    }
+    if (op != GP_SIN && op != GP_COS && op != GP_EXPC && op != GP_PLOG) {
+        // the binary functions that leave the core: protected division, >, <, ==, AND, OR
         float A[T], B[T];
         core_gather_or_const<T, V0>(oa, fl & 1u, cbits, A);
         core_gather_or_const<T, V0>(ob, fl & 2u, cbits, B);
+        switch (op) {
+            case GP_PDIV:
 #pragma unroll
-        for (int j = 0; j < T; j++) A[j] = pdiv(A[j], B[j]);
+                for (int j = 0; j < T; j++) A[j] = pdiv(A[j], B[j]);
+                break;
+            case GP_GT:
+#pragma unroll
+                for (int j = 0; j < T; j++) A[j] = (A[j] > B[j]) ? 1.0f : 0.0f;
+                break;
+            case GP_LT:
+#pragma unroll
+                for (int j = 0; j < T; j++) A[j] = (A[j] < B[j]) ? 1.0f : 0.0f;
+                break;
+            case GP_EQ:
+#pragma unroll
+                for (int j = 0; j < T; j++) A[j] = (A[j] == B[j]) ? 1.0f : 0.0f;
+                break;
+            case GP_AND:
+#pragma unroll
+                for (int j = 0; j < T; j++) A[j] = (A[j] != 0.0f && B[j] != 0.0f) ? 1.0f : 0.0f;
+                break;
+            default:   // GP_OR
+#pragma unroll
+                for (int j = 0; j < T; j++) A[j] = (A[j] != 0.0f || B[j] != 0.0f) ? 1.0f : 0.0f;
+                break;
+        }
         core_scatter<T, V0>(od, A);
         return;
     }
@@ -128,7 +171,7 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             uint64_t table;
             uint32_t probe = a.probe;
             asm volatile("" : "+s"(probe));
-            Core<T, D, NF, V0, (MODE >= 2 ? MODE : 0)>::run(code, off, pay, cst, probe, pf_end,
+            Core<T, D, NF, V0, (MODE == 4 ? 3 : (MODE >= 2 ? MODE : 0))>::run(code, off, pay, cst, probe, pf_end,
                                                             (uint32_t)a.prefetch, table);
             // later passes skip the prefetch; an opaque 0, so the first pass is not peeled off
             pf_end = 0u;
@@ -140,7 +183,7 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
             more = ((pay >> 24) & 15u) != CORE_OP_END;
             if (more) {
                 // Boolean programs never leave the core before their end
-                if constexpr (MODE != 2) do_exit<T, V0, MODE != 0>(pay, cst, tab);
+                if constexpr (MODE != 2) do_exit<T, V0, MODE == 1 || MODE == 3>(pay, cst, tab);
                 off += 16u;
             }
         }
@@ -173,13 +216,15 @@ __device__ __forceinline__ void process_unit(const CoreArgs& a, const float* X, 
                     eq += ok ? (uint32_t)__popc(~(__float_as_uint(o[j]) ^ yw) & mask) : 0u;
                 }
                 v = wave_sum((double)eq);
-            } else if (kind == GP_FIT_HITS) {
+            } else if (kind == GP_FIT_HITS || kind == GP_FIT_CLASS_ERR) {
+                // hits: the sign rule; class errors: rint(o) is not the class y
+                const bool cls = kind == GP_FIT_CLASS_ERR;
                 uint32_t hits = 0;
 #pragma unroll
                 for (int j = 4 * k; j < 4 * k + 4; j++) {
                     const bool ok = 64 * j + (int64_t)lane < left;
                     const float yj = ok ? yt[64 * j + lane] : 0.0f;
-                    const bool hit = ok && ((o[j] > 0.0f) == (yj > 0.0f));
+                    const bool hit = ok && (cls ? !(rintf(o[j]) == yj) : ((o[j] > 0.0f) == (yj > 0.0f)));
                     hits += (uint32_t)__popcll(__ballot(hit));
                 }
                 v = (double)hits;
@@ -214,7 +259,7 @@ template <int T, int D, int NF, int V0, int MODE>
 __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
     // the transcendentals' reduction tables, copied into LDS by the whole block
     const double* tab = nullptr;
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 0 || MODE == 4) {
         __shared__ __attribute__((aligned(16))) double s_tab[gmath::kTabSize];
         gmath::tab_fill(s_tab, (int)threadIdx.x, (int)blockDim.x);
         __syncthreads();
@@ -296,7 +341,8 @@ __device__ __forceinline__ void k_core_body(const CoreArgs& a) {
 // One kernel per variant.  amdgpu_num_vgpr(n) lets the compiler allocate 2n
 // VGPRs on gfx950 (checked at build time against the compiler's
 // reserved-register report); the core owns v[V0 ...].  MODE: 0 full, 1 no
-// sin/cos/exp/log code (for programs without them), 2 Boolean.
+// sin/cos/exp/log code (for programs without them), 2 Boolean, 3 trees only
+// without sin/cos/exp/log code, 4 trees only with it.
 #define GPX_KERNEL(T, D, NF, V0, MODE, NAME)                                                            \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr((V0) / 2))) void                   \
         k_core_##NAME(CoreArgs a) {                                                                     \

@@ -45,6 +45,10 @@ int core_reg_levels(int vi) {
     return v.arith >= 2 || v.d > GPX_LIN_REGS ? v.d : GPX_LIN_REGS;
 }
 
+// Kernel modes (gen_core.py): 0 full, 1 without sin/cos/exp/log code, 2 Boolean, 3 trees only without
+// sin/cos/exp/log code, 4 trees only with it.
+static bool mode_no_transc(int mode) { return mode == 1 || mode == 2 || mode == 3; }
+
 int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean, bool trees_only) {
     // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
     // outside the core) run best with room for that code (no spills) and as
@@ -61,7 +65,7 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
     auto score = [&](const CoreVariantDesc& v) {
         if (heavy) return (v.ncv >= 64) * 100000000 + waves(v) * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
         // trees-only kernels first (the smallest handler tables), then those without sin/cos/exp/log code
-        return (v.arith == 3) * 400000000 + (v.arith != 0) * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 -
+        return (v.arith == 3) * 400000000 + mode_no_transc(v.arith) * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 -
                v.nf * 100 - v.n / 100;
     };
     // Boolean programs: the most slots in flight per SIMD (waves x tile width)
@@ -70,8 +74,8 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
         if ((v.arith == 2) != boolean) continue;
-        if (v.arith == 3 && !trees_only) continue;
-        if (v.nf < n_load || v.d < depth || (v.arith && has_transc)) continue;
+        if (v.arith >= 3 && !trees_only) continue;
+        if (v.nf < n_load || v.d < depth || (mode_no_transc(v.arith) && has_transc)) continue;
         if (best < 0) { best = i; continue; }
         const bool better = boolean ? score_bool(v) > score_bool(kCoreVariants[best])
                                     : score(v) > score(kCoreVariants[best]);
@@ -158,8 +162,11 @@ struct Emitter {
     }
 };
 
-bool is_core_op(uint32_t op) {
-    return op == GP_ADD || op == GP_SUB || op == GP_MUL || (op >= GP_AND && op <= GP_NOR);
+// Functions the core applies itself: + - * and, in Boolean kernels, the four
+// bitwise functions; the others leave the core (in arithmetic trees opcodes 8
+// and 9 are the logical AND and OR, which are exits).
+bool is_core_op(uint32_t op, bool boolean) {
+    return op == GP_ADD || op == GP_SUB || op == GP_MUL || (boolean && op >= GP_AND && op <= GP_NOR);
 }
 
 }  // namespace
@@ -176,20 +183,36 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
         int h;  // stack height before the instruction
         switch (mode) {
             case M_SS: case M_SSR: h = ha + 1; break;
+            case M_S3: h = ha + 2; break;
             case M_XX: case M_XC: case M_CX: case M_X: case M_C: h = ha - 1; break;
             default: h = ha; break;
         }
         const int xa = FO + fa * T, xb = FO + fb * T;
         if (op == OP_PUSH) {
             if (mode == M_X) {
-                if (h != 0) { snprintf(err, 256, "push of a variable above the stack bottom"); return GP_E_INVAL; }
-                e.put(CK_PUSHX, 0, 0, 0, (uint32_t)xa, 0);
+                // Boolean kernels push a variable only as a whole program, at the bottom
+                if (v.arith == 2 && h != 0) {
+                    snprintf(err, 256, "push of a variable above the stack bottom");
+                    return GP_E_INVAL;
+                }
+                e.put(CK_PUSHX, 0, h, 0, (uint32_t)xa, 0);
             } else {
                 e.put(CK_PUSHC, 0, 0, 0, (uint32_t)(h * T), c);
             }
             continue;
         }
-        if (is_core_op(op)) {
+        if (mode == M_S3) {
+            // IF: operands at positions fa, fb and the third of s[h-3 .. h-1]; the exit writes
+            // the lowest of the three offsets
+            const int pc = 3 - fa - fb;
+            if (op != OP_IF || fa > 2 || fb > 2 || pc < 0 || pc > 2 || fa == fb || h < 3) {
+                snprintf(err, 256, "malformed three-operand instruction");
+                return GP_E_INVAL;
+            }
+            e.exit(OP_IF, (h - 3 + fa) * T, (h - 3 + fb) * T, (h - 3 + pc) * T, false, false, 0);
+            continue;
+        }
+        if (is_core_op(op, v.arith == 2)) {
             const bool comm = op != GP_SUB;
             switch (mode) {
                 case M_SS: e.put(CK_SS, op, 0, 0, (uint32_t)((h - 2) * T), 0); break;
@@ -230,7 +253,7 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
             }
             continue;
         }
-        // protected division and the transcendentals leave the core
+        // protected division, the transcendentals and the classification functions leave the core
         switch (mode) {
             case M_SS: e.exit(op, (h - 2) * T, (h - 1) * T, (h - 2) * T, false, false, 0); break;
             case M_SSR: e.exit(op, (h - 1) * T, (h - 2) * T, (h - 2) * T, false, false, 0); break;
@@ -264,11 +287,11 @@ static int translate_linear(const uint32_t* w, int64_t n, const uint32_t* cst, i
         const int d = (int)((wd >> 8) & 255u), s1 = (int)((wd >> 16) & 255u), s2 = (int)(wd >> 24);
         const bool c1 = s1 >= GP_SRC_CONST, c2 = s2 >= GP_SRC_CONST;
         const uint32_t v1 = c1 ? cst[s1 - GP_SRC_CONST] : 0u, v2 = c2 ? cst[s2 - GP_SRC_CONST] : 0u;
-        if (op >= GP_SIN) {  // unary: leave the core
+        if (op >= GP_SIN && op <= GP_PLOG) {  // unary: leave the core
             e.exit(op, c1 ? 0 : off(s1), 0, d * T, c1, false, v1);
             continue;
         }
-        if (op == GP_PDIV) {
+        if (!is_core_op(op, false)) {   // protected division and the classification functions
             if (c1 && c2) {
                 e.put(CK_MOVC, 0, d, 0, 0, v1);
                 e.exit(op, d * T, 0, d * T, false, true, v2);
@@ -355,7 +378,7 @@ int core_variant_t(int vi) { return kCoreVariants[vi].t; }
 int core_variant_ncv(int vi) { return kCoreVariants[vi].ncv; }
 int core_variant_d(int vi) { return kCoreVariants[vi].d; }
 int core_variant_nf(int vi) { return kCoreVariants[vi].nf; }
-int core_variant_arith(int vi) { return kCoreVariants[vi].arith != 0; }
+int core_variant_arith(int vi) { return mode_no_transc(kCoreVariants[vi].arith); }
 bool core_variant_bool(int vi) { return kCoreVariants[vi].arith == 2; }
 bool core_variant_trees_only(int vi) { return kCoreVariants[vi].arith >= 2; }
 

@@ -55,6 +55,7 @@ bool is_bool_op(int op) { return op >= GP_AND && op <= GP_NOR; }
 int arity(int32_t t) {
     const int op = t & 0xFF;
     if (op == GP_VAR || op == GP_CONST) return 0;
+    if (op == GP_IF) return 3;
     return (op >= GP_SIN && op <= GP_PLOG) ? 1 : 2;
 }
 
@@ -150,15 +151,20 @@ gp_status check_config(const gp_evolve_config* c, int32_t n_feat, bool* boolean,
     funs.clear();
     for (int op = 0; op < 32; op++)
         if (c->functions & (1u << op)) {
-            if (op > GP_NOR) return fail(GP_E_INVAL, "function bit %d is not an opcode", op);
+            if (op > GP_IF) return fail(GP_E_INVAL, "function bit %d is not an opcode", op);
             funs.push_back(op);
         }
     if (funs.empty()) return fail(GP_E_INVAL, "empty function set");
-    const bool b = is_bool_op(funs[0]);
+    // a Boolean set holds only the four bitwise functions; an arithmetic set may hold AND and OR
+    // (logical there) but not NAND or NOR
+    bool b = true;
+    for (int op : funs) b = b && is_bool_op(op);
     for (int op : funs)
-        if (is_bool_op(op) != b) return fail(GP_E_INVAL, "Boolean and arithmetic functions mixed");
+        if (!b && (op == GP_NAND || op == GP_NOR))
+            return fail(GP_E_INVAL, "NAND and NOR belong to the Boolean set; arithmetic functions mixed in");
     if (b && c->kind != GP_FIT_HITS) return fail(GP_E_INVAL, "Boolean runs use GP_FIT_HITS");
-    if (!b && c->kind != GP_FIT_MSE && c->kind != GP_FIT_SUM_ABS && c->kind != GP_FIT_HITS)
+    if (!b && c->kind != GP_FIT_MSE && c->kind != GP_FIT_SUM_ABS && c->kind != GP_FIT_HITS &&
+        c->kind != GP_FIT_CLASS_ERR)
         return fail(GP_E_INVAL, "unknown fitness kind %d", c->kind);
     *boolean = b;
     return GP_OK;
@@ -288,7 +294,8 @@ gp_status gp_evolve(const gp_evolve_config* cfg, const void* X, int32_t n_feat, 
     if (!X || !y || !res) return fail(GP_E_INVAL, "null X, y or result");
     if (n_cases < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
     hipStream_t s = (hipStream_t)stream;
-    const bool hits = cfg->kind == GP_FIT_HITS;
+    const bool hits = cfg->kind == GP_FIT_HITS;                       // maximised
+    const bool counts = hits || cfg->kind == GP_FIT_CLASS_ERR;        // int32 fitness
     const int32_t P = cfg->pop_size;
     void* d_out = nullptr;
     hipError_t e = hipMalloc(&d_out, (size_t)P * 4);
@@ -322,7 +329,7 @@ gp_status gp_evolve(const gp_evolve_config* cfg, const void* X, int32_t n_feat, 
             st = gp_eval_tree(tok.data(), cst.data(), off.data(), P, (const float*)X, n_feat, n_cases,
                               (const float*)y, cfg->kind, d_out, stream);
         if (st != GP_OK) break;
-        e = hipMemcpyAsync(hits ? (void*)fit_i.data() : (void*)fit_f.data(), d_out, (size_t)P * 4,
+        e = hipMemcpyAsync(counts ? (void*)fit_i.data() : (void*)fit_f.data(), d_out, (size_t)P * 4,
                            hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
@@ -335,7 +342,7 @@ gp_status gp_evolve(const gp_evolve_config* cfg, const void* X, int32_t n_feat, 
         // the best program so far (lower score is better: errors, or minus the hits)
         int32_t gbest = 0;
         for (int32_t p = 0; p < P; p++) {
-            const double v = hits ? -(double)fit_i[p] : (double)fit_f[p];
+            const double v = hits ? -(double)fit_i[p] : (counts ? (double)fit_i[p] : (double)fit_f[p]);
             score[p] = std::isnan(v) ? INFINITY : v;
             if (score[p] < score[gbest]) gbest = p;
         }

@@ -53,9 +53,11 @@ LIN_REGS = 8              # register slots reserved for linear programs (and sta
 # small, so nothing spills), 2 for the Boolean function set (slots are
 # 32-bit words of bit-packed cases), 3 like 1 for trees only (no linear
 # handlers or registers: a handler table half the size, and the stack
-# levels start the VGPR range).  Work that leaves the core (sin/cos/
-# exp/log in binary64, protected division) runs in the compiler's VGPRs:
-# programs rich in it take a variant with room for it.
+# levels start the VGPR range), 4 like 0 for trees only (the core of mode
+# 3 with the sin/cos/exp/log code: room for many feature slots).  Work that
+# leaves the core (sin/cos/exp/log in binary64, protected division, the
+# classification functions) runs in the compiler's VGPRs: programs rich in
+# it take a variant with room for it.
 VARIANTS = [
     (8, 6, 8, 40, 0),
     (8, 6, 8, 128, 0),
@@ -75,6 +77,8 @@ VARIANTS = [
     (4, 12, 32, 40, 1),
     (8, 6, 8, 56, 3),
     (8, 8, 8, 40, 3),
+    (4, 8, 16, 48, 3),
+    (4, 8, 44, 48, 4),
     (8, 6, 20, 48, 2),
     (8, 8, 20, 32, 2),
     (4, 12, 32, 40, 2),
@@ -83,9 +87,9 @@ VARIANTS = [
 
 def vname(v):
     """Kernel name suffix of a variant: T_D_NF_NCV, plus _a when it has no
-    sin/cos/exp/log code, _at when it also runs trees only, and _b for the
-    Boolean function set."""
-    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], ("", "_a", "_b", "_at")[v[4]])
+    sin/cos/exp/log code, _at when it also runs trees only, _t for trees only
+    with that code, and _b for the Boolean function set."""
+    return "%d_%d_%d_%d%s" % (v[0], v[1], v[2], v[3], ("", "_a", "_b", "_at", "_t")[v[4]])
 
 OPS = {"add": "v_add_f32_e32", "sub": "v_sub_f32_e32", "mul": "v_mul_f32_e32"}
 OP_ID = {"add": 0, "sub": 1, "mul": 2}
@@ -144,7 +148,7 @@ def gen_variant(T, D, NF, NCV, mode=0):
     assert FO + NF * T <= 256, "index range exceeds 8 bits"
     assert V0 + FO + NF * T <= 256
     assert NCV % 8 == 0
-    tag = "T%dD%dF%dV%d%s" % (T, D, NF, NCV, {2: "B", 3: "R"}.get(mode, ""))
+    tag = "T%dD%dF%dV%d%s" % (T, D, NF, NCV, {2: "B", 3: "R", 4: "R"}.get(mode, ""))
     hs = []
 
     def prologue(h, const=False, second_index=False, index=None):
@@ -271,12 +275,13 @@ def gen_variant(T, D, NF, NCV, mode=0):
             valu(h, "v_sub_f32_e32 %s, s72, %s" % (vr(V0 + l * T + j), vr(V0 + j)))
         epilogue(h)
         hs.append(h)
-    h = Handler(K["PUSHX"])                        # s[0] = x[a] (a program that is one variable)
-    prologue(h, index=["SRC0"])
-    for j in range(T):
-        valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + j), vr(V0 + j)))
-    epilogue(h)
-    hs.append(h)
+    for l in range(D):
+        h = Handler(K["PUSHX"], 0, l)              # s[l] = x[a] (a lone variable, an operand of IF)
+        prologue(h, index=["SRC0"])
+        for j in range(T):
+            valu(h, "v_mov_b32_e32 %s, %s" % (vr(V0 + l * T + j), vr(V0 + j)))
+        epilogue(h)
+        hs.append(h)
     h = Handler(K["PUSHC"])                        # s[l] = c; index l*T
     prologue(h, const=True, index=["DST"])
     for j in range(T):
@@ -284,7 +289,7 @@ def gen_variant(T, D, NF, NCV, mode=0):
     epilogue(h)
     hs.append(h)
 
-    if mode == 3:                      # trees only: no linear handlers
+    if mode >= 3:                      # trees only: no linear handlers
         return finish(hs, tag, V0, FO)
 
     # ---------------------------------------------------------------- linear
@@ -580,7 +585,7 @@ def main(out_dir):
     seen = {}
     for (T, D, NF, NCV, AR) in VARIANTS:
         B = AR == 2
-        core = (T, D, NF, NCV, AR if AR >= 2 else 0)   # modes 0 and 1 share a core
+        core = (T, D, NF, NCV, {1: 0, 4: 3}.get(AR, AR))   # modes 0 and 1 share a core, so do 3 and 4
         if core in seen:
             host.append((T, D, NF, NCV, AR) + seen[core])
             continue

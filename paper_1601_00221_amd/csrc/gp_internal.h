@@ -10,7 +10,7 @@ namespace gpx {
 // (the paper's linear form, section 5): each function reads its operands
 // from a case input X, a constant C or the stack S and pushes its result.
 // Two 32-bit words per instruction:
-//   w0 bits 0-3   op    (GP function 0-11, or OP_PUSH)
+//   w0 bits 0-3   op    (GP function 0-9 or 12-14, OP_IF, or OP_PUSH)
 //      bits 4-7   mode  (where the operands come from, see below)
 //      bits 8-15  feature index of operand A (X modes)
 //      bits 16-23 feature index of operand B (X modes)
@@ -19,6 +19,9 @@ namespace gpx {
 // h is the stack height before the instruction; s[0] is the bottom.
 // ---------------------------------------------------------------------------
 enum : uint32_t { OP_PUSH = 15 };
+// The three-operand IF (public opcode GP_IF) in the 4-bit op field: 10 is
+// NAND, a function of the Boolean set only, so no arithmetic tree uses it.
+enum : uint32_t { OP_IF = 10 };
 
 enum : uint32_t {
     M_SS = 0,   // A = s[h-2], B = s[h-1]  -> s[h-2], h-1
@@ -33,6 +36,8 @@ enum : uint32_t {
     M_S = 9,    // unary, in place on s[h-1]
     M_X = 10,   // unary on X_a, pushed (OP_PUSH: push X_a)
     M_C = 11,   // unary on c, pushed   (OP_PUSH: push c)
+    M_S3 = 12,  // three operands s[h-3], s[h-2], s[h-1] -> s[h-3], h-2; operand A is the value at
+                //   position fa (0 = s[h-3]), B at position fb, C at the remaining one (IF only)
 };
 
 inline uint32_t enc_w0(uint32_t op, uint32_t mode, uint32_t fa, uint32_t fb, uint32_t h_after) {

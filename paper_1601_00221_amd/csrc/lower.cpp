@@ -12,9 +12,16 @@
 // register-resident stack holds every program of realistic size.  When the
 // right operand of a non-commutative function ran first, the instruction is
 // marked reversed so the operand order of the tree is kept.
+//
+// The three-operand IF of the classification function set (section 4.2) has
+// no form with X or C operands: its terminal operands are pushed, its
+// subtrees run in order of decreasing stack need, and the instruction reads
+// the three values from the top of the stack, recording where each operand
+// landed.
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/gp.h"
@@ -32,14 +39,18 @@ static int arity_of(int op, int opset = OPSET_REAL) {
     }
     switch (op) {
         case GP_ADD: case GP_SUB: case GP_MUL: case GP_PDIV: return 2;
+        case GP_AND: case GP_OR: case GP_GT: case GP_LT: case GP_EQ: return 2;   // logical AND, OR here
+        case GP_IF: return 3;
         case GP_SIN: case GP_COS: case GP_EXPC: case GP_PLOG: return 1;
         case GP_VAR: case GP_CONST: return 0;
         default: return -1;
     }
 }
 
-// the four Boolean functions are symmetric, like + and *
-static bool commutative(int op) { return op == GP_ADD || op == GP_MUL || (op >= GP_AND && op <= GP_NOR); }
+// the four Boolean functions are symmetric, like + and *, and so are ==, logical AND and OR
+static bool commutative(int op) {
+    return op == GP_ADD || op == GP_MUL || (op >= GP_AND && op <= GP_NOR) || op == GP_EQ;
+}
 
 static uint32_t fbits(float f) {
     uint32_t u;
@@ -59,7 +70,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
         return GP_E_DEPTH;
     }
     const int32_t N = (int32_t)n;
-    std::vector<int32_t> kid(2 * (size_t)N, -1);
+    std::vector<int32_t> kid(3 * (size_t)N, -1);
     std::vector<int8_t> ar(N);
     std::vector<int8_t> filled(N, 0);
     std::vector<int32_t> open;
@@ -89,7 +100,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
                 return GP_E_INVAL;
             }
             const int32_t p = open.back();
-            kid[2 * (size_t)p + filled[p]] = i;
+            kid[3 * (size_t)p + filled[p]] = i;
             if (++filled[p] == ar[p]) open.pop_back();
         }
         if (a > 0) open.push_back(i);
@@ -102,14 +113,33 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
 
     // Stack levels each subtree needs when its terminals are read as operands.
     std::vector<int32_t> need(N, 0);
+    // IF: its three operands in the order they are evaluated (decreasing need, ties left to right)
+    auto if_order = [&](int32_t i, int32_t ord[3]) {
+        int32_t nd[3];
+        for (int k = 0; k < 3; k++) {
+            const int32_t c = kid[3 * (size_t)i + k];
+            nd[k] = ar[c] == 0 ? 1 : need[c];
+            ord[k] = k;
+        }
+        for (int x = 1; x < 3; x++)
+            for (int y = x; y > 0 && nd[ord[y]] > nd[ord[y - 1]]; y--) std::swap(ord[y], ord[y - 1]);
+        int32_t m = 0;
+        for (int k = 0; k < 3; k++) m = std::max(m, nd[ord[k]] + k);
+        return m;
+    };
     for (int32_t i = N - 1; i >= 0; i--) {
         if (ar[i] == 0) continue;
-        const int32_t a = kid[2 * (size_t)i];
+        const int32_t a = kid[3 * (size_t)i];
+        if (ar[i] == 3) {
+            int32_t ord[3];
+            need[i] = if_order(i, ord);
+            continue;
+        }
         if (ar[i] == 1) {
             need[i] = ar[a] == 0 ? 1 : need[a];
             continue;
         }
-        const int32_t b = kid[2 * (size_t)i + 1];
+        const int32_t b = kid[3 * (size_t)i + 1];
         const bool ta = ar[a] == 0, tb = ar[b] == 0;
         if (ta && tb) need[i] = 1;
         else if (tb) need[i] = need[a];
@@ -135,13 +165,17 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
     auto feat = [&](int32_t i) -> uint32_t { return (uint32_t)tok[i] >> 8; };
     auto is_var = [&](int32_t i) { return (tok[i] & 0xFF) == GP_VAR; };
 
+    auto push_terminal = [&](int32_t i) {
+        if (is_var(i)) emit(OP_PUSH, M_X, feat(i), 0, 0.0f, +1, 0, false, 0);
+        else emit(OP_PUSH, M_C, 0, 0, cst[i], +1, 0, false, 0);
+    };
+
     struct Frame { int32_t node; int32_t stage; };
     std::vector<Frame> fr;
     fr.reserve(64);
     if (ar[0] == 0) {
         // A lone terminal: push it.
-        if (is_var(0)) emit(OP_PUSH, M_X, feat(0), 0, 0.0f, +1, 0, false, 0);
-        else emit(OP_PUSH, M_C, 0, 0, cst[0], +1, 0, false, 0);
+        push_terminal(0);
     } else {
         fr.push_back({0, 0});
     }
@@ -149,7 +183,24 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
         Frame& f = fr.back();
         const int32_t i = f.node;
         const int op = tok[i] & 0xFF;
-        const int32_t a = kid[2 * (size_t)i];
+        const int32_t a = kid[3 * (size_t)i];
+        if (ar[i] == 3) {
+            int32_t ord[3];
+            if_order(i, ord);
+            if (f.stage < 3) {
+                const int32_t c = kid[3 * (size_t)i + ord[f.stage]];
+                f.stage++;
+                if (ar[c] == 0) push_terminal(c);
+                else fr.push_back({c, 0});
+                continue;
+            }
+            // operand ord[k] is the k-th of the three values from the bottom
+            uint32_t pos[3];
+            for (int k = 0; k < 3; k++) pos[ord[k]] = (uint32_t)k;
+            emit(OP_IF, M_S3, pos[0], pos[1], 0.0f, -2, 3, true, 3);
+            fr.pop_back();
+            continue;
+        }
         if (ar[i] == 1) {
             if (ar[a] == 0) {
                 if (is_var(a)) emit(op, M_X, feat(a), 0, 0.0f, +1, 0, true, 1);
@@ -164,7 +215,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
             }
             continue;
         }
-        const int32_t b = kid[2 * (size_t)i + 1];
+        const int32_t b = kid[3 * (size_t)i + 1];
         const bool ta = ar[a] == 0, tb = ar[b] == 0;
         if (ta && tb) {
             if (is_var(a) && is_var(b)) emit(op, M_XX, feat(a), feat(b), 0.0f, +1, 0, true, 2);
@@ -238,7 +289,7 @@ int check_linear(const uint32_t* code, int64_t n, int64_t n_cst, int32_t n_reg, 
         const int op = wd & 0xFF;
         const int a = arity_of(op);
         const uint32_t dst = (wd >> 8) & 0xFF;
-        if (a < 1) {
+        if (a < 1 || a > 2) {
             snprintf(err, 256, "instruction %lld: opcode %d is not a function", (long long)i, op);
             return GP_E_INVAL;
         }

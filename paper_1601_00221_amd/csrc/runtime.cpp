@@ -142,6 +142,8 @@ Workspace& workspace(hipStream_t s) {
 static uint32_t op_cost(uint32_t op) {
     switch (op) {
         case GP_PDIV: return 12;
+        case GP_AND: case GP_OR: case GP_GT: case GP_LT: case GP_EQ: return 10;   // exits of a few instructions
+        case OP_IF: return 12;
         case GP_SIN: case GP_COS: return 40;
         case GP_EXPC: case GP_PLOG: return 24;
         default: return 1;
@@ -252,8 +254,9 @@ gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cs
             const uint32_t wd = src[i];
             const int op = wd & 0xFF;
             cost += op_cost(op);
-            pd.n_transc += (op >= GP_SIN);
-            const int na = op < GP_SIN ? 2 : 1;
+            const bool unary = op >= GP_SIN && op <= GP_PLOG;
+            pd.n_transc += unary;
+            const int na = unary ? 1 : 2;
             for (int q = 0; q < na; q++) {
                 const int id = (int)((wd >> (16 + 8 * q)) & 0xFF);
                 if (id >= n_reg && id < GP_SRC_CONST) max_feat = std::max(max_feat, id - n_reg);
@@ -463,7 +466,7 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     if (!X) return fail(GP_E_INVAL, "X is null");
     if (!out) return fail(GP_E_INVAL, "out is null");
     if (N < 1) return fail(GP_E_INVAL, "n_cases must be >= 1");
-    if (kind < GP_FIT_SUM_ABS || kind > GP_OUT_CASES) return fail(GP_E_INVAL, "unknown fitness kind %d", kind);
+    if (kind < GP_FIT_SUM_ABS || kind > GP_FIT_CLASS_ERR) return fail(GP_E_INVAL, "unknown fitness kind %d", kind);
     if (kind != GP_OUT_CASES && !y) return fail(GP_E_INVAL, "y is null");
     if (n_feat < pd.n_feat) return fail(GP_E_INVAL, "case matrix has %d features, programs need %d", n_feat, pd.n_feat);
     if (pd.n_prog == 0) return GP_OK;
@@ -473,7 +476,15 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     if (boolean != (n_bits > 0)) return fail(GP_E_INVAL, "internal: Boolean programs need a bit count");
     if (boolean && kind != GP_FIT_HITS && kind != GP_OUT_CASES)
         return fail(GP_E_INVAL, "Boolean programs take GP_FIT_HITS or GP_OUT_CASES, not kind %d", kind);
-    const int vi = opt && opt->variant >= 0 ? opt->variant : default_variant(pd);
+    int vi = opt && opt->variant >= 0 ? opt->variant : default_variant(pd);
+    if (!(opt && opt->variant >= 0) && !(opt && opt->no_alloc)) {
+        // GP2D_VARIANT (tuning): a kernel variant index to use instead, if it can hold the programs
+        const int32_t ev = env_int("GP2D_VARIANT", 0) - 1;
+        if (ev >= 0 && ev < core_variants() && core_variant_nf(ev) >= pd.n_load && core_variant_d(ev) >= pd.max_depth &&
+            !(core_variant_arith(ev) && pd.n_transc > 0) && core_variant_bool(ev) == (pd.opset == OPSET_BOOL) &&
+            !(core_variant_trees_only(ev) && pd.form != FORM_TREE))
+            vi = ev;
+    }
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth ||

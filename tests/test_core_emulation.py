@@ -181,11 +181,18 @@ class CoreEmu:
         oa, ob, od = pay & 255, (pay >> 8) & 255, (pay >> 16) & 255
         op, fl = (pay >> 24) & 15, pay >> 28
         c = np.frombuffer(np.uint32(cst).tobytes(), np.float32)[0]
+        if op == 10:   # IF: the third operand's offset in the destination byte, result to the lowest
+            A, B, C = self.gather(oa), self.gather(ob), self.gather(od)
+            self.scatter(min(oa, ob, od), np.where(A != 0, B, C).astype(np.float32))
+            return
         A = np.full((self.T, 64), c, np.float32) if fl & 1 else self.gather(oa)
         if op == synth.PDIV:
             B = np.full((self.T, 64), c, np.float32) if fl & 2 else self.gather(ob)
             with np.errstate(all="ignore"):
                 R = np.where(np.abs(B) < f32(1e-6), f32(1.0), (A / B).astype(np.float32))
+        elif op in (synth.AND, synth.OR, synth.GT, synth.LT, synth.EQ):
+            B = np.full((self.T, 64), c, np.float32) if fl & 2 else self.gather(ob)
+            R = np.vectorize(lambda x, z: oracle.apply(op, x, z), otypes=[np.float32])(A, B)
         else:
             R = np.vectorize(lambda x: oracle.apply(op, x), otypes=[np.float32])(A)
         self.scatter(od, R.astype(np.float32))
@@ -251,6 +258,25 @@ def test_core_trees_match_oracle(vi):
         got = emu.evaluate(words, prog_off, X, n_load)
         ref = oracle.tree_outputs(pp.tok, pp.cst, pp.off, X)
         assert _same(got, ref).all()
+
+
+@pytest.mark.parametrize("vi", [i for i in REAL if gen_core.VARIANTS[i][2] >= 9][:1] +
+                         [i for i, v in enumerate(gen_core.VARIANTS) if v[4] in (3, 4) and v[2] >= 9])
+def test_core_classification_match_oracle(vi):
+    """Trees over the classification functions (comparisons, logical AND and
+    OR, the three-operand IF; their terminal operands pushed at any level)
+    run through the generated handlers and the kernel's exits to the
+    oracle's bits."""
+    T, D, NF, NCV = gen_core.VARIANTS[vi][:4]
+    F = 9
+    rng = synth.rng_for(500 + vi)
+    pop = synth.ptc2_population(rng, 40, synth.SHUTTLE_SET, F, 1, 80, 0.2, crange=(-3.0, 3.0))
+    X = np.round(synth.uniform_cases(rng, F, 64 * T + 11, -3, 3))
+    emu = CoreEmu(vi)
+    words, prog_off = gp.core_lower(pop, F, vi, BASE)
+    got = emu.evaluate(words, prog_off, X, F)
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    assert _same(got, ref).all()
 
 
 @pytest.mark.parametrize("vi", LINEAR)

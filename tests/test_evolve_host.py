@@ -16,7 +16,7 @@ def arity(t):
     op = t & 0xFF
     if op in (synth.VAR, synth.CONST):
         return 0
-    return 1 if synth.SIN <= op <= synth.PLOG else 2
+    return synth.ARITY[op]
 
 
 def depth(tok):
@@ -38,7 +38,7 @@ def check_population(tok, cst, off, cfg, n_feat, fset):
     assert len(off) == cfg.pop_size + 1 and off[0] == 0
     X = synth.uniform_cases(synth.rng_for(1), n_feat, 3, -1, 1)
     # the oracle accepts every program (well-formed, features in range)
-    if synth.AND in fset:
+    if set(fset) <= set(synth.BOOL_SET):
         Xw = np.zeros((n_feat, 1), np.uint32)
         oracle.bool_outputs(tok, off, Xw)
     else:
@@ -134,6 +134,25 @@ def test_boolean_runs():
     check_population(tok, cst, off, cfg, 6, synth.BOOL_SET)
 
 
+def test_classification_runs():
+    """The classification set (three-operand IF, logical AND and OR): the
+    host steps keep every program well formed and lowerable, and class
+    errors are a minimised fitness."""
+    cfg = gp.evolve_config(synth.SHUTTLE_SET, kind="class_err", pop_size=120, p_const=0.1,
+                           const_range=(-200.0, 200.0), seed=21)
+    tok, cst, off = gp.init_population(cfg, 9)
+    check_population(tok, cst, off, cfg, 9, synth.SHUTTLE_SET)
+    assert np.any((tok & 0xFF) == synth.IF)
+    score = np.arange(120, dtype=np.float64)
+    nt, nc, no = gp.breed(cfg, tok, cst, off, 9, score, 5)
+    check_population(nt, nc, no, cfg, 9, synth.SHUTTLE_SET)
+    for p in range(0, 120, 7):
+        gp.gp_lower_tree(nt[no[p]:no[p + 1]], nc[no[p]:no[p + 1]], 9)
+    # NAND cannot join an arithmetic set
+    with pytest.raises(gp.GPError):
+        gp.init_population(gp.evolve_config(synth.SHUTTLE_SET + (synth.NAND,), kind="class_err"), 9)
+
+
 def test_config_errors():
     bad = [gp.evolve_config(ARITH + synth.BOOL_SET),                 # mixed sets
            gp.evolve_config(synth.BOOL_SET, kind="mse"),             # Boolean with an error measure
@@ -148,5 +167,5 @@ def test_config_errors():
     tok, cst, off = gp.init_population(cfg, 2)
     with pytest.raises(gp.GPError):                                  # a parent with a foreign opcode
         t2 = tok.copy()
-        t2[0] = synth.AND
+        t2[0] = synth.NAND
         gp.breed(cfg, t2, cst, off, 2, np.zeros(10), 1)

@@ -84,7 +84,9 @@ def test_bool_rejects():
     ok = bp.pop_of(bp.fn(synth.AND, bp.var(0), bp.var(1)))
     with pytest.raises(gp.GPError):
         gp.gp_eval_bool(ok.tok, ok.off, Xw, Xw[0], "mse", out, 128)
-    # the arithmetic entry points reject Boolean functions
+    # the arithmetic entry points reject the bitwise-only functions (AND and OR are
+    # logical there, a classification function)
+    nand = bp.pop_of(bp.fn(synth.NAND, bp.var(0), bp.var(1)))
     with pytest.raises(gp.GPError):
-        gp.gp_eval_tree(ok.tok, np.zeros(3, np.float32), ok.off, torch.zeros((2, 8), device="cuda"), None,
+        gp.gp_eval_tree(nand.tok, np.zeros(3, np.float32), nand.off, torch.zeros((2, 8), device="cuda"), None,
                         "cases", torch.empty((1, 8), device="cuda"))

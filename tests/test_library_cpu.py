@@ -45,19 +45,30 @@ def test_worked_example_lowering_counts():
 
 
 # --- a test-side reader of the lowered words, to check the lowering on the CPU
-MODES = dict(SS=0, SSR=1, SX=2, XS=3, SC=4, CS=5, XX=6, XC=7, CX=8, S=9, X=10, C=11)
+MODES = dict(SS=0, SSR=1, SX=2, XS=3, SC=4, CS=5, XX=6, XC=7, CX=8, S=9, X=10, C=11, S3=12)
+OP_IF = 10     # the three-operand IF in a lowered word
 
 
 def run_lowered(words, X):
     """Evaluate lowered words on every case with numpy float32 arithmetic
-    (+ - * /p only; other ops are not used with this reader)."""
+    (+ - * /p and the classification functions; transcendentals are not used
+    with this reader)."""
     F, N = X.shape
     st = []
     w = words.reshape(-1, 2)
+    t = lambda m: m.astype(np.float32)
     for w0, w1 in w:
         op, mode, fa, fb, hafter = w0 & 15, (w0 >> 4) & 15, (w0 >> 8) & 255, (w0 >> 16) & 255, w0 >> 24
         c = np.frombuffer(np.uint32(w1).tobytes(), np.float32)[0]
         cv = np.full(N, c, np.float32)
+        if mode == 12:
+            assert op == OP_IF
+            three = st[-3:]
+            del st[-3:]
+            A, B, C = three[fa], three[fb], three[3 - fa - fb]
+            st.append(np.where(A != 0, B, C).astype(np.float32))
+            assert len(st) == hafter
+            continue
         if mode in (0, 1):
             b2, b1 = st.pop(), st.pop()
             A, B = (b1, b2) if mode == 0 else (b2, b1)
@@ -76,6 +87,11 @@ def run_lowered(words, X):
             elif op == 1: R = A - B
             elif op == 2: R = A * B
             elif op == 3: R = np.where(np.abs(B) < np.float32(1e-6), np.float32(1), A / B)
+            elif op == 8: R = t((A != 0) & (B != 0))
+            elif op == 9: R = t((A != 0) | (B != 0))
+            elif op == 12: R = t(A > B)
+            elif op == 13: R = t(A < B)
+            elif op == 14: R = t(A == B)
             elif op == 15: R = A          # push
             else: raise AssertionError("op")
         st.append(R.astype(np.float32))
@@ -98,6 +114,28 @@ def test_lowering_preserves_values_bit_exact():
         same = (got.view(np.int32) == ref[p].view(np.int32)) | (np.isnan(got) & np.isnan(ref[p]))
         assert same.all(), p
     assert nrev > 0   # the reversed (right-first) operand order was exercised
+
+
+def test_lowering_classification_trees_bit_exact():
+    """Trees over the classification set (>, <, ==, AND, OR, IF and + - * /)
+    lower to words that the test-side reader evaluates to the oracle's bits:
+    IF's operands run in order of decreasing need and are read from where
+    they landed on the stack."""
+    rng = synth.rng_for(15)
+    pop = synth.ptc2_population(rng, 300, synth.SHUTTLE_SET, 5, 1, 150, 0.2, crange=(-3.0, 3.0))
+    X = np.round(synth.uniform_cases(rng, 5, 41, -3, 3))      # small integers: comparisons often tie
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    n_if = 0
+    for p in range(pop.n_prog):
+        t, c = pop.program(p)
+        words, st = gp.gp_lower_tree(t, c, 5)
+        n_if += int(np.sum((t & 0xFF) == synth.IF))
+        got = run_lowered(words, X)
+        same = (got.view(np.int32) == ref[p].view(np.int32)) | (np.isnan(got) & np.isnan(ref[p]))
+        assert same.all(), p
+        # every IF reads three stack values; its terminal operands are pushed
+        assert st["n_values"] == sum(1 + synth.ARITY[int(o)] for o in (t & 0xFF) if int(o) < 64)
+    assert n_if > 100
 
 
 def test_lowering_depth_bound():
