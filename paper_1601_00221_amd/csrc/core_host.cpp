@@ -20,11 +20,43 @@ namespace gpx {
 
 namespace {
 
+// Handler slot by key: an open-addressing table (a few thousand keys, one
+// lookup per translated instruction).
+struct SlotTable {
+    std::vector<uint32_t> keys;   // 0xFFFFFFFF = empty (no handler key has it)
+    std::vector<uint16_t> slots;
+    uint32_t mask = 0;
+    static uint32_t hash(uint32_t k) { return (k * 0x9E3779B1u) ^ (k >> 15); }
+    void build(const std::vector<std::pair<uint32_t, uint16_t>>& kv) {
+        uint32_t cap = 16;
+        while (cap < 2 * kv.size()) cap <<= 1;
+        keys.assign(cap, 0xFFFFFFFFu);
+        slots.assign(cap, 0);
+        mask = cap - 1;
+        for (auto& e : kv) {
+            uint32_t i = hash(e.first) & mask;
+            while (keys[i] != 0xFFFFFFFFu && keys[i] != e.first) i = (i + 1) & mask;
+            keys[i] = e.first;
+            slots[i] = e.second;
+        }
+    }
+    bool find(uint32_t k, uint16_t* out) const {
+        if (keys.empty()) return false;
+        for (uint32_t i = hash(k) & mask;; i = (i + 1) & mask) {
+            if (keys[i] == k) {
+                *out = slots[i];
+                return true;
+            }
+            if (keys[i] == 0xFFFFFFFFu) return false;
+        }
+    }
+};
+
 struct VariantMap {
     bool ready = false;
     int device = -1;
     uint64_t base = 0;
-    std::unordered_map<uint32_t, uint16_t> slot;
+    SlotTable slot;
 };
 
 std::mutex g_mu;
@@ -36,6 +68,17 @@ uint32_t key_of(int kind, int op, int p1, int p2) {
 }
 
 }  // namespace
+
+static SlotTable variant_slots(int vi) {
+    const CoreVariantDesc& v = kCoreVariants[vi];
+    std::vector<std::pair<uint32_t, uint16_t>> kv;
+    kv.reserve(v.n);
+    for (int i = 0; i < v.n; i++)
+        kv.push_back({key_of(v.keys[i].kind, v.keys[i].op, v.keys[i].p1, v.keys[i].p2), v.slots[i]});
+    SlotTable t;
+    t.build(kv);
+    return t;
+}
 
 const CoreVariantDesc& core_desc(int vi) { return kCoreVariants[vi]; }
 int core_variants() { return (int)(sizeof(kCoreVariants) / sizeof(kCoreVariants[0])); }
@@ -103,13 +146,11 @@ gp_status core_ready(int vi, hipStream_t s) {
     uint64_t base = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&base, d, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(d);
+    (void)hipFree(d);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "handler table probe: %s", hipGetErrorString(e));
     if (base == 0 || (base & (GPX_SLOT - 1)) != 0) return fail(GP_E_DEVICE, "handler table probe returned %llx",
                                                                (unsigned long long)base);
-    const CoreVariantDesc& v = kCoreVariants[vi];
-    m.slot.clear();
-    for (int i = 0; i < v.n; i++) m.slot[key_of(v.keys[i].kind, v.keys[i].op, v.keys[i].p1, v.keys[i].p2)] = v.slots[i];
+    m.slot = variant_slots(vi);
     m.base = base;
     m.device = dev;
     m.ready = true;
@@ -130,26 +171,36 @@ namespace {
 // core -- a program's start, the return from an exit -- begins with A.
 constexpr int kPhaseB = 0x80;
 
+// Writes core instructions (4 words each) to `out`, at most `cap` of them.
 struct Emitter {
     const VariantMap& m;
-    std::vector<uint32_t>& out;
+    uint32_t* out;
+    int64_t cap;
     char* err;
+    int64_t n = 0;
     bool ok = true;
     int phase = 0;
 
     void put(int kind, int op, int p1, int p2, uint32_t pay, uint32_t cst) {
-        auto it = m.slot.find(key_of(kind | phase, op, p1, p2));
+        uint16_t slot = 0;
+        const bool have = m.slot.find(key_of(kind | phase, op, p1, p2), &slot);
         phase ^= kPhaseB;
-        if (it == m.slot.end()) {
+        if (!have) {
             snprintf(err, 256, "no core handler for kind %d op %d (%d, %d)", kind, op, p1, p2);
             ok = false;
             return;
         }
-        const uint64_t addr = m.base + (uint64_t)it->second * GPX_SLOT;
-        out.push_back((uint32_t)addr);
-        out.push_back((uint32_t)(addr >> 32));
-        out.push_back(pay);
-        out.push_back(cst);
+        if (n >= cap) {
+            snprintf(err, 256, "internal: core code longer than counted");
+            ok = false;
+            return;
+        }
+        const uint64_t addr = m.base + (uint64_t)slot * GPX_SLOT;
+        uint32_t* o = out + 4 * n++;
+        o[0] = (uint32_t)addr;
+        o[1] = (uint32_t)(addr >> 32);
+        o[2] = pay;
+        o[3] = cst;
     }
     // leave the core: operation op on A (offset or constant), B, into D
     void exit(uint32_t op, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
@@ -171,11 +222,11 @@ bool is_core_op(uint32_t op, bool boolean) {
 
 }  // namespace
 
-static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const VariantMap& m, std::vector<uint32_t>& out,
-                          char* err) {
+static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const VariantMap& m, uint32_t* out,
+                          int64_t cap, int64_t* n_out, char* err) {
     const CoreVariantDesc& v = kCoreVariants[vi];
     const int T = v.t, FO = core_reg_levels(vi) * T;
-    Emitter e{m, out, err};
+    Emitter e{m, out, cap, err};
     for (int64_t i = 0; i < n_instr && e.ok; i++) {
         const uint32_t w0 = w[2 * i], c = w[2 * i + 1];
         const uint32_t op = w0 & 15u, mode = (w0 >> 4) & 15u;
@@ -270,14 +321,27 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
         }
     }
     if (e.ok) e.exit(CORE_OP_END, 0, 0, 0, false, false, 0);
+    *n_out = e.n;
     return e.ok ? GP_OK : GP_E_INVAL;
 }
 
+// Core instructions of a register program: the register set-up, one or two
+// per instruction, and the end.
+static int64_t linear_records(const uint32_t* w, int64_t n, int32_t n_reg) {
+    int64_t k = n_reg + n + 1;
+    for (int64_t i = 0; i < n; i++) {
+        const uint32_t op = w[i] & 255u;
+        const bool c1 = ((w[i] >> 16) & 255u) >= GP_SRC_CONST, c2 = (w[i] >> 24) >= GP_SRC_CONST;
+        k += (c1 && c2 && !(op >= GP_SIN && op <= GP_PLOG));
+    }
+    return k;
+}
+
 static int translate_linear(const uint32_t* w, int64_t n, const uint32_t* cst, int32_t n_reg, int32_t n_feat, int vi,
-                            const VariantMap& m, std::vector<uint32_t>& out, char* err) {
+                            const VariantMap& m, uint32_t* out, int64_t cap, int64_t* n_out, char* err) {
     const CoreVariantDesc& v = kCoreVariants[vi];
     const int T = v.t, FO = core_reg_levels(vi) * T;
-    Emitter e{m, out, err};
+    Emitter e{m, out, cap, err};
     auto off = [&](int id) { return id < n_reg ? id * T : FO + (id - n_reg) * T; };
     // registers start as r[k] = x[k mod n_feat]
     for (int k = 0; k < n_reg && e.ok; k++) e.put(CK_MOVX, 0, k, 0, (uint32_t)(FO + (k % n_feat) * T), 0);
@@ -320,40 +384,72 @@ static int translate_linear(const uint32_t* w, int64_t n, const uint32_t* cst, i
         }
     }
     if (e.ok) e.exit(CORE_OP_END, 0, 0, 0, false, false, 0);
+    *n_out = e.n;
     return e.ok ? GP_OK : GP_E_INVAL;
 }
 
 static VariantMap map_at(int vi, uint64_t base) {
     VariantMap m;
-    const CoreVariantDesc& v = kCoreVariants[vi];
-    for (int i = 0; i < v.n; i++) m.slot[key_of(v.keys[i].kind, v.keys[i].op, v.keys[i].p1, v.keys[i].p2)] = v.slots[i];
+    m.slot = variant_slots(vi);
     m.base = base;
     m.ready = true;
     return m;
 }
 
+// Programs are translated in parallel, each into its own counted range of
+// the code: a tree gives one core instruction per lowered instruction plus
+// the end; a register program as linear_records counts.
 static gp_status translate_with(const ProgData& pd, int vi, const VariantMap& m, std::vector<uint32_t>& code,
                                 std::vector<DevProg>& progs) {
-    code.clear();
+    const int32_t P = pd.n_prog;
     progs = pd.progs;
-    char err[256];
-    for (int32_t p = 0; p < pd.n_prog; p++) {
+    std::vector<int64_t> start((size_t)P + 1, 0);
+    for (int32_t p = 0; p < P; p++) {
         const DevProg& src = pd.progs[p];
-        const size_t start = code.size();
-        int rc;
-        if ((src.meta & 1u) == FORM_TREE)
-            rc = translate_tree(pd.code.data() + src.code_off, src.len, vi, m, code, err);
-        else
-            rc = translate_linear(pd.code.data() + src.code_off, src.len, pd.code.data() + src.code_off + src.len,
-                                  pd.n_reg, pd.n_feat, vi, m, code, err);
-        if (rc != GP_OK) return fail((gp_status)rc, "program %d: %s", p, err);
-        if (code.size() * 4 > 0xFFFFFFF0ull) return fail(GP_E_INVAL, "programs exceed 4 GiB of core code");
-        progs[p].code_off = (uint32_t)start;   // words
-        progs[p].len = (uint32_t)((code.size() - start) / 4);
+        const int64_t k = (src.meta & 1u) == FORM_TREE ? (int64_t)src.len + 1
+                                                        : linear_records(pd.code.data() + src.code_off, src.len,
+                                                                         pd.n_reg);
+        start[p + 1] = start[p] + k;
     }
+    if (start[P] * 16 > 0xFFFFFFF0ll) return fail(GP_E_INVAL, "programs exceed 4 GiB of core code");
     // the core reads records two at a time, up to one record past a program's
-    // last one: pad the end of the code
-    code.insert(code.end(), 16, 0u);
+    // last one: the code ends with padding
+    code.assign((size_t)start[P] * 4 + 16, 0u);
+    std::vector<int32_t> rc((size_t)P, GP_OK);
+    parallel_for(P, [&](int64_t p0, int64_t p1) {
+        char err[256];
+        for (int64_t p = p0; p < p1; p++) {
+            const DevProg& src = pd.progs[p];
+            uint32_t* out = code.data() + 4 * start[p];
+            const int64_t cap = start[p + 1] - start[p];
+            int64_t n = 0;
+            if ((src.meta & 1u) == FORM_TREE)
+                rc[p] = translate_tree(pd.code.data() + src.code_off, src.len, vi, m, out, cap, &n, err);
+            else
+                rc[p] = translate_linear(pd.code.data() + src.code_off, src.len,
+                                         pd.code.data() + src.code_off + src.len, pd.n_reg, pd.n_feat, vi, m, out,
+                                         cap, &n, err);
+            if (rc[p] == GP_OK && n != cap) rc[p] = GP_E_INVAL;
+        }
+    });
+    for (int32_t p = 0; p < P; p++) {
+        if (rc[p] != GP_OK) {
+            // translate the first failing program again on this thread for its message
+            const DevProg& src = pd.progs[p];
+            std::vector<uint32_t> tmp(4 * (size_t)(start[p + 1] - start[p] + 8));
+            char err[256] = "internal: core code length differs from its count";
+            int64_t n = 0;
+            if ((src.meta & 1u) == FORM_TREE)
+                translate_tree(pd.code.data() + src.code_off, src.len, vi, m, tmp.data(), (int64_t)tmp.size() / 4, &n,
+                               err);
+            else
+                translate_linear(pd.code.data() + src.code_off, src.len, pd.code.data() + src.code_off + src.len,
+                                 pd.n_reg, pd.n_feat, vi, m, tmp.data(), (int64_t)tmp.size() / 4, &n, err);
+            return fail((gp_status)rc[p], "program %d: %s", p, err);
+        }
+        progs[p].code_off = (uint32_t)(4 * start[p]);   // words
+        progs[p].len = (uint32_t)(start[p + 1] - start[p]);
+    }
     return GP_OK;
 }
 

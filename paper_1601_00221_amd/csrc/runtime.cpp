@@ -8,10 +8,14 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -61,7 +65,7 @@ gp_status DevBuf::reserve(size_t n) {
 }
 
 void DevBuf::release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     cap = 0;
 }
@@ -79,7 +83,7 @@ gp_status Staging::begin(size_t n) {
         if (e != hipSuccess) return fail(GP_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
     }
     if (n > h.cap) {
-        if (h.host) hipHostFree(h.host);
+        if (h.host) (void)hipHostFree(h.host);
         h.host = nullptr;
         h.cap = 0;
         size_t want = n < 65536 ? 65536 : n + n / 4;
@@ -115,9 +119,9 @@ gp_status Staging::end(hipStream_t s) {
 
 void Staging::release() {
     for (Half& h : half) {
-        if (h.pending && h.ev) hipEventSynchronize(h.ev);
-        if (h.host) hipHostFree(h.host);
-        if (h.ev) hipEventDestroy(h.ev);
+        if (h.pending && h.ev) (void)hipEventSynchronize(h.ev);
+        if (h.host) (void)hipHostFree(h.host);
+        if (h.ev) (void)hipEventDestroy(h.ev);
         h = Half();
     }
     used = 0;
@@ -133,6 +137,86 @@ Workspace& workspace(hipStream_t s) {
     Workspace* w = new Workspace();  // lives until process exit
     g_ws[s] = w;
     return *w;
+}
+
+// ---------------------------------------------------------------------------
+// Host threads: a fixed pool that splits a range of programs
+// ---------------------------------------------------------------------------
+namespace {
+struct Pool {
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::vector<std::thread> th;
+    const std::function<void(int64_t, int64_t)>* fn = nullptr;
+    int64_t n = 0, chunk = 1;
+    std::atomic<int64_t> next{0};
+    int active = 0;
+    uint64_t gen = 0;
+    bool stop = false;
+
+    explicit Pool(int k) {
+        for (int i = 0; i < k; i++) th.emplace_back([this] { worker(); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        for (auto& t : th) t.join();
+    }
+    void take() {
+        for (;;) {
+            const int64_t lo = next.fetch_add(chunk);
+            if (lo >= n) return;
+            (*fn)(lo, std::min(n, lo + chunk));
+        }
+    }
+    void worker() {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            cv.wait(lk, [&] { return stop || gen != seen; });
+            if (stop) return;
+            seen = gen;
+            lk.unlock();
+            take();
+            lk.lock();
+            if (--active == 0) done_cv.notify_all();
+        }
+    }
+    void run(int64_t count, const std::function<void(int64_t, int64_t)>& f) {
+        std::unique_lock<std::mutex> lk(mu);
+        fn = &f;
+        n = count;
+        chunk = std::max<int64_t>(1, count / (8 * (int64_t)(th.size() + 1)));
+        next = 0;
+        active = (int)th.size();
+        gen++;
+        cv.notify_all();
+        lk.unlock();
+        take();
+        lk.lock();
+        done_cv.wait(lk, [&] { return active == 0; });
+        fn = nullptr;
+    }
+};
+
+std::mutex g_pool_mu;   // one parallel_for at a time (calls from several host threads take turns)
+}  // namespace
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
+    if (n <= 0) return;
+    if (n < 64) {
+        fn(0, n);
+        return;
+    }
+    static Pool* pool = [] {
+        const unsigned hc = std::thread::hardware_concurrency();
+        return new Pool((int)std::max(1u, std::min(16u, hc ? hc : 1u)) - 1);   // the caller is the last thread
+    }();
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    pool->run(n, fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -169,44 +253,65 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
         if (n > GP_MAX_LEN) return fail(GP_E_DEPTH, "program %d: %lld nodes exceeds %d", p, (long long)n, GP_MAX_LEN);
         total += n;
     }
-    pd.code.resize((size_t)total * 2);  // at most one instruction per node
+    if (total > 0x7FFFFFFFll) return fail(GP_E_INVAL, "programs exceed 2^31 nodes");
+    // Program p is lowered at word 2 * off[p] (at most one instruction per
+    // node), so the programs are independent: they are lowered in parallel.
+    pd.code.resize((size_t)total * 2);
     pd.progs.resize(P);
     pd.cost.resize(P);
-    int64_t w = 0;
+    std::vector<TreeLowering> lst(P);
+    std::vector<int32_t> pfeat(P, -1), prc(P, GP_OK), ptransc(P, 0);
+    parallel_for(P, [&](int64_t p0, int64_t p1) {
+        char err[256];
+        for (int64_t p = p0; p < p1; p++) {
+            const int64_t n = off[p + 1] - off[p];
+            uint32_t* words = pd.code.data() + 2 * off[p];
+            const int rc = lower_tree(tok + off[p], cst ? cst + off[p] : nullptr, n, n_feat, words, &lst[p], err, opset);
+            if (rc != GP_OK) {
+                prc[p] = rc;
+                return;
+            }
+            int32_t mf = -1;
+            for (int64_t i = 0; i < n; i++) {
+                const int32_t t = tok[off[p] + i];
+                if ((t & 0xFF) == GP_VAR) mf = std::max<int32_t>(mf, (int32_t)((uint32_t)t >> 8));
+            }
+            pfeat[p] = mf;
+            uint32_t cost = 0;
+            int32_t nt = 0;
+            for (int32_t i = 0; i < lst[p].n_instr; i++) {
+                const uint32_t op = words[2 * i] & 15u;
+                cost += op_cost(op);
+                nt += (op >= GP_SIN && op <= GP_PLOG);
+            }
+            ptransc[p] = nt;
+            pd.cost[p] = cost + 8;
+        }
+    });
     int32_t max_feat = -1;
-    char err[256];
     for (int32_t p = 0; p < P; p++) {
-        const int64_t n = off[p + 1] - off[p];
-        TreeLowering st;
-        int rc = lower_tree(tok + off[p], cst ? cst + off[p] : nullptr, n, n_feat, pd.code.data() + 2 * w, &st, err,
-                            opset);
-        if (rc != GP_OK) return fail((gp_status)rc, "program %d: %s", p, err);
-        for (int64_t i = 0; i < n; i++) {
-            const int32_t t = tok[off[p] + i];
-            if ((t & 0xFF) == GP_VAR) max_feat = std::max<int32_t>(max_feat, (int32_t)((uint32_t)t >> 8));
+        if (prc[p] != GP_OK) {
+            // lower the first failing program again on this thread for its message
+            char err[256];
+            TreeLowering st;
+            lower_tree(tok + off[p], cst ? cst + off[p] : nullptr, off[p + 1] - off[p], n_feat, nullptr, &st, err,
+                       opset);
+            return fail((gp_status)prc[p], "program %d: %s", p, err);
         }
-        uint32_t cost = 0;
-        for (int32_t i = 0; i < st.n_instr; i++) {
-            const uint32_t op = pd.code[2 * (w + i)] & 15u;
-            cost += op_cost(op);
-            pd.n_transc += (op >= GP_SIN && op <= GP_PLOG);
-        }
-        if (w > 0xFFFFFFFFll - 2 * (int64_t)st.n_instr)
-            return fail(GP_E_INVAL, "programs exceed 2^32 device words");
+        const TreeLowering& st = lst[p];
         DevProg& d = pd.progs[p];
-        d.code_off = (uint32_t)(2 * w);
+        d.code_off = (uint32_t)(2 * off[p]);
         d.len = (uint32_t)st.n_instr;
         d.meta = FORM_TREE | ((uint32_t)st.max_depth << 8);
         d.reserved0 = 0;
         d.reserved1 = 0;
         d.row = (uint64_t)p;
-        pd.cost[p] = cost + 8;
+        max_feat = std::max(max_feat, pfeat[p]);
+        pd.n_transc += ptransc[p];
         pd.max_depth = std::max(pd.max_depth, st.max_depth);
         pd.n_instr += st.n_instr;
         pd.n_gpop += st.n_nodes;
-        w += st.n_instr;
     }
-    pd.code.resize((size_t)w * 2);
     pd.n_load = max_feat + 1 > 0 ? max_feat + 1 : 1;
     return GP_OK;
 }
@@ -787,6 +892,8 @@ gp_status gp_core_lower_linear(const uint32_t* code, const int64_t* off, const f
                                int32_t n_prog, int32_t n_reg, int32_t n_feat, int32_t variant, uint64_t table_base,
                                uint32_t* words, int64_t max_words, int64_t* prog_off, int64_t* n_words) {
     clear_error();
+    if (variant < 0 || variant >= core_variants()) return fail(GP_E_INVAL, "variant %d does not exist", variant);
+    if (core_variant_trees_only(variant)) return fail(GP_E_INVAL, "variant %d runs trees only", variant);
     ProgData pd;
     gp_status st = build_linear(code, off, cst, cst_off, n_prog, n_reg, n_feat, pd);
     if (st != GP_OK) return st;

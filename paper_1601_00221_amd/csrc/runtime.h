@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -102,7 +103,7 @@ struct DevProgs {
         progs.release();
         groups_by_G.clear();
         groups_once.release();
-        if (ready) hipEventDestroy(ready);
+        if (ready) (void)hipEventDestroy(ready);
         ready = nullptr;
     }
 };
@@ -131,6 +132,9 @@ struct EvalOptions {
 };
 
 Workspace& workspace(hipStream_t s);
+// Run fn over [0, n) split into chunks on a pool of host threads (the caller
+// takes part); small ranges run on the calling thread.  Calls take turns.
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn);
 int32_t code_prefetch();
 
 // Kernel timing brackets (active only while gp_timing_enable(1)).
