@@ -509,6 +509,63 @@ def bench_served(args):
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "requests": int(len(lat)),
                 "span_s": span, "mean_batch": st["mean_batch"], "batches": st["batches"]}, results
 
+    def run_open(batching, rate, seed=55):
+        """Open loop: the measured requests (those after each run's warm-up)
+        arrive as one Poisson stream of `rate` requests per second, taken
+        round robin over the runs, whether or not earlier ones are done."""
+        srv = gp.Server(batching=batching)
+        ids = [srv.add_dataset(X, y) for X, y in data]
+        order = [(ri, k) for k in range(n_warm, args.requests) for ri in range(len(w.runs))]
+        at = np.cumsum(synth.rng_for(seed).exponential(1.0 / rate, len(order)))
+        pending = []
+        lock = threading.Lock()
+        lat, results, errors = [], {}, []
+        gpop_meas = [0]
+        t_done = [0.0]
+
+        def waiter(ri, k, tk, t_arr, out):
+            # one thread per request, started at its arrival: completion is seen when it happens
+            try:
+                rc = srv.wait(tk)
+                t1 = time.perf_counter()
+                if rc != 0:
+                    raise gp.GPError(rc, gp.last_error())
+                srv.release(tk)
+                with lock:
+                    lat.append(t1 - t_arr)
+                    gpop_meas[0] += reqs[ri][k][1]
+                    t_done[0] = max(t_done[0], t1)
+                    results[(ri, k)] = out
+            except Exception as e:   # reported after the join
+                errors.append(repr(e))
+
+        t0 = time.perf_counter()
+        for i, (ri, k) in enumerate(order):
+            dt = t0 + at[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            pop = reqs[ri][k][0]
+            out = gp.out_tensor("mse", pop.n_prog, 0)
+            t_arr = time.perf_counter()
+            tk = srv.submit(gp.make_job(pop, ids[ri], "mse", out))
+            th = threading.Thread(target=waiter, args=(ri, k, tk, t_arr, out))
+            th.start()
+            pending.append(th)
+            if (i + 1) % 256 == 0:
+                log("  %s: %d requests submitted" % ("served" if batching else "one launch per request", i + 1))
+        for th in pending:
+            th.join()
+        st = srv.stats()
+        srv.close()
+        if errors:
+            raise RuntimeError("open-loop run failed: " + errors[0])
+        lat = np.sort(np.array(lat))
+        span = t_done[0] - t0
+        return {"gpops_per_s": gpop_meas[0] / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "requests": int(len(lat)),
+                "span_s": span, "offered_requests_per_s": rate, "mean_batch": st["mean_batch"],
+                "batches": st["batches"]}, results
+
     gp.timing_read(reset=True)
     gp.timing_enable(True)
     served, res_b = run_mode(True)
@@ -519,6 +576,22 @@ def bench_served(args):
     single, res_s = run_mode(False)
     log("one launch per request", single)
     same = all(torch.equal(res_b[k].view(torch.int32), res_s[k].view(torch.int32)) for k in res_b)
+    open_loop = None
+    if args.open_load > 0:
+        # offered load: a fraction of the closed loop's served throughput, in requests per second
+        mean_gpop = float(np.mean([g for lst in reqs for _, g in lst[n_warm:]]))
+        rate = args.open_load * served["gpops_per_s"] / mean_gpop
+        log("open loop at %.2f requests/s (%.0f %% of the served closed-loop rate)" % (rate, 100 * args.open_load))
+        o_b, ob_res = run_open(True, rate)
+        log("open loop, served", o_b)
+        o_s, os_res = run_open(False, rate)
+        log("open loop, one launch per request", o_s)
+        open_loop = {"load_fraction": args.open_load, "served": o_b,
+                     "unbatched": dict(o_s, speedup_of_served=o_b["gpops_per_s"] / o_s["gpops_per_s"]),
+                     "fitness_identical": all(torch.equal(ob_res[k].view(torch.int32), os_res[k].view(torch.int32))
+                                              for k in ob_res) and
+                                          all(torch.equal(ob_res[k].view(torch.int32), res_b[k].view(torch.int32))
+                                              for k in ob_res)}
     config = {"workload": w.name, "n_runs": len(w.runs), "requests_per_run": args.requests,
               "warmup_requests_per_run": n_warm, "gpop_total": total_gpop, "fitness": "mse",
               "arrivals": "closed loop, Exp(2 ms) think time"}
@@ -527,6 +600,8 @@ def bench_served(args):
     res["served"] = served
     res["unbatched"] = dict(single, speedup_of_served=served["gpops_per_s"] / single["gpops_per_s"],
                             fitness_identical=same)
+    if open_loop is not None:
+        res["open_loop"] = open_loop
     # kernel time over all batched launches of the served run (warm-up included)
     all_gpop = total_gpop
     res["roofline"] = roofline(all_gpop / max(n_launch, 1), kernel_ms / 1e3 / max(n_launch, 1), "k_core", w.name)
@@ -747,6 +822,8 @@ def main():
     ap.add_argument("--no-arith", action="store_true", help="scale-tree: skip the {+,-,*} sub-measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--requests", type=int, default=10, help="served: requests per run")
+    ap.add_argument("--open-load", type=float, default=0.0,
+                    help="served: also run an open loop at this fraction of the closed loop's served rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the evaluator is built and measured on a single MI355X "

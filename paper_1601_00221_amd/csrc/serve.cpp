@@ -115,12 +115,16 @@ static void finish_batch(Server& S, InFlight& f, gp_status st) {
     }
     S.bytes_in_flight -= f.bytes;
     if (f.stream >= 0) S.stream_busy[f.stream] = false;
-    if (f.ev) hipEventDestroy(f.ev);
+    if (f.ev) (void)hipEventDestroy(f.ev);
     f.ev = nullptr;
 }
 
-// Launch one batch of admitted requests on stream slot k (lock held).
-static gp_status launch_batch_locked(Server& S, int k, std::vector<std::shared_ptr<Request>>& reqs, InFlight& f) {
+// Launch one batch of admitted requests on stream slot k.  Runs on the
+// scheduler thread without the server lock: it reads only the immutable
+// configuration, the stream's own scratch and the taken requests (ds is a
+// copy of the dataset list).
+static gp_status launch_batch(Server& S, const std::vector<gp_dataset>& ds, int k,
+                              std::vector<std::shared_ptr<Request>>& reqs, InFlight& f) {
     std::vector<BatchJobRef> refs;
     for (auto& r : reqs) refs.push_back(BatchJobRef{&r->pd, r->ds, r->kind, r->out});
     f.stream = k;
@@ -140,10 +144,20 @@ static gp_status launch_batch_locked(Server& S, int k, std::vector<std::shared_p
     gp_status st = core_ready(c.variant, s);
     if (st != GP_OK) return st;
     BatchPlan plan;
-    st = plan_batch(refs, S.datasets, c, plan);
+    st = plan_batch(refs, ds, c, plan);
     if (st != GP_OK) return st;
     BatchScratch& sc = *S.scratch[k];
     std::lock_guard<std::mutex> g(sc.mu);
+    // The stream's buffers only grow; when they hold more than this batch needs and more than the
+    // stream's share of the budget, free them first, so memory held between batches stays bounded
+    // (the free waits for the device, which is rare: only after an unusually large batch).
+    const size_t held = sc.code.cap + sc.progs.cap + sc.order.cap + sc.units.cap + sc.jobs.cap + sc.datasets.cap +
+                        sc.reduce.cap + sc.partials.cap + sc.counter.cap;
+    const size_t need = plan_device_bytes(plan);
+    if (held > need && held > S.cfg.memory_budget / (size_t)S.cfg.n_streams) {
+        sc.code.release(); sc.progs.release(); sc.order.release(); sc.units.release(); sc.jobs.release();
+        sc.datasets.release(); sc.reduce.release(); sc.partials.release(); sc.counter.release();
+    }
     if ((st = upload_plan(plan, sc, s)) != GP_OK) return st;
     if ((st = launch_plan(plan, sc, s)) != GP_OK) return st;
     hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
@@ -212,16 +226,21 @@ static void scheduler(Server* Sp) {
             S.n_admitted += (int64_t)take.size();
             S.n_batches++;
             S.n_batched_reqs += (int64_t)take.size();
-            S.inflight.emplace_back();
-            InFlight& f = S.inflight.back();
+            InFlight f;
             f.bytes = bytes;
             S.bytes_in_flight += bytes;
             S.stream_busy[k] = true;
-            gp_status st = launch_batch_locked(S, k, take, f);
+            // plan, translate, upload and launch without the lock, so clients keep submitting,
+            // polling and waiting meanwhile
+            const std::vector<gp_dataset> ds = S.datasets;
+            lk.unlock();
+            gp_status st = launch_batch(S, ds, k, take, f);
+            lk.lock();
             if (st != GP_OK) {
                 finish_batch(S, f, st);
-                S.inflight.pop_back();
                 S.cv_done.notify_all();
+            } else {
+                S.inflight.push_back(f);
             }
         }
         // 3. sleep until something changes; poll the device while batches run
@@ -264,7 +283,7 @@ gp_status gp_serve_create(const gp_serve_config* cfg, gp_server** out) {
         if (!S.cfg.dry_run) {
             hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
             if (e != hipSuccess) {
-                for (hipStream_t x : S.streams) hipStreamDestroy(x);
+                for (hipStream_t x : S.streams) (void)hipStreamDestroy(x);
                 return fail(GP_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
             }
         }
@@ -463,7 +482,7 @@ gp_status gp_serve_destroy(gp_server* sv) {
     if (S.th.joinable()) S.th.join();   // drains batches already on the device
     S.cv_done.notify_all();
     for (hipStream_t s : S.streams)
-        if (s) hipStreamDestroy(s);
+        if (s) (void)hipStreamDestroy(s);
     for (auto& sc : S.scratch) {
         sc->code.release(); sc->progs.release(); sc->order.release(); sc->units.release();
         sc->jobs.release(); sc->datasets.release(); sc->reduce.release(); sc->partials.release();
