@@ -308,21 +308,25 @@ static gp_status time_config(const std::vector<BatchJobRef>& jobs, const std::ve
         return fail(GP_E_DEVICE, "hipEventCreate failed");
     std::vector<float> t;
     for (int r = 0; r < reps; r++) {
-        hipEventRecord(e0, s);
+        hipError_t e = hipEventRecord(e0, s);
         st = launch_plan(plan, sc, s);
-        hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (st != GP_OK) break;
-        hipError_t e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
         if (e != hipSuccess) {
             st = fail(GP_E_DEVICE, "hipEventSynchronize: %s", hipGetErrorString(e));
             break;
         }
         float x = 0;
-        hipEventElapsedTime(&x, e0, e1);
+        e = hipEventElapsedTime(&x, e0, e1);
+        if (e != hipSuccess) {
+            st = fail(GP_E_DEVICE, "hipEventElapsedTime: %s", hipGetErrorString(e));
+            break;
+        }
         t.push_back(x);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != GP_OK) return st;
     std::sort(t.begin(), t.end());
     *ms = t[t.size() / 2];
