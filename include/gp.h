@@ -33,9 +33,10 @@
  *   - Arithmetic: IEEE binary32, round to nearest even, no contraction,
  *     denormals kept.  pdiv(a,b) = |b| < 1e-6f ? 1 : a/b; plog(a) =
  *     |a| < 1e-6f ? 0 : log|a|; expc(a) = exp(min(a, 88)) with NaN passing
- *     through; sin/cos/exp/log are evaluated in binary64 by the device math
- *     library and rounded once to binary32 (within 2 ulp of the exact value,
- *     and almost always the correctly rounded one).  The paper names these
+ *     through; sin/cos/exp/log are evaluated in binary64 (the library's own
+ *     table-driven range reduction and polynomials, no math-library call)
+ *     and rounded once to binary32 (within 2 ulp of the exact value, and
+ *     almost always the correctly rounded one).  The paper names these
  *     functions without defining their protection.
  *   - Fitness: d = out - y in binary32; sum of |d|, mean of d*d, or the
  *     number of cases with (out > 0) == (y > 0) (Table 2: mean squared error
@@ -101,7 +102,12 @@ enum {
 #define GP_SRC_CONST 128
 #define GP_MAX_REG 8          /* registers of a linear program */
 #define GP_MAX_FEAT 44        /* features a program may read (the KDD Cup 99 shape has 41) */
-#define GP_MAX_DEPTH 12       /* stack levels of a lowered tree */
+/* Stack levels of a lowered tree.  Every tree of at most GP_MAX_LEN nodes
+ * needs at most 20 (at most 15 without IF), so this limit never rejects a
+ * valid tree; programs needing more than 12 run on deep kernel variants with
+ * fewer waves per SIMD.  With more than 32 features read, 12 levels is the
+ * most the register file holds beside them: deeper programs get GP_E_DEPTH. */
+#define GP_MAX_DEPTH 20
 #define GP_MAX_LEN 65536      /* instructions (tree nodes) per program */
 
 /* ------------------------------------------------------------------------ */
@@ -118,11 +124,13 @@ gp_status gp_eval_tree(const int32_t* tok, const float* cst, const int64_t* off,
                        const float* X, int32_t n_feat, int64_t n_cases, const float* y,
                        int32_t kind, void* out, void* stream);
 
-/* Evaluate n_prog register linear programs over n_reg registers.  code/off
- * are HOST arrays in CSR form; cst/cst_off (HOST, may be NULL when no
- * program uses a constant) hold each program's constant table.  Registers
- * start as r[k] = x[k mod n_feat]; the output is r[0]; unary functions read
- * src1 only. */
+/* Evaluate n_prog register linear programs over n_reg registers: the
+ * register-machine linear GP form that section 5 compares against the tree
+ * form (Table 8), in which each instruction reads two registers, inputs or
+ * constants and writes one register.  code/off are HOST arrays in CSR form;
+ * cst/cst_off (HOST, may be NULL when no program uses a constant) hold each
+ * program's constant table.  Registers start as r[k] = x[k mod n_feat]; the
+ * output is r[0]; unary functions read src1 only. */
 gp_status gp_eval_linear(const uint32_t* code, const int64_t* off, const float* cst,
                          const int64_t* cst_off, int32_t n_prog, int32_t n_reg,
                          const float* X, int32_t n_feat, int64_t n_cases, const float* y,

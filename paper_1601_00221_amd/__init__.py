@@ -22,6 +22,7 @@ GP_OK, GP_E_INVAL, GP_E_NOMEM, GP_E_DEPTH, GP_E_DEVICE, GP_E_AGAIN, GP_E_NOTFOUN
     0, -1, -2, -3, -4, -5, -6, -7
 GP_FIT_SUM_ABS, GP_FIT_MSE, GP_FIT_HITS, GP_OUT_CASES, GP_FIT_CLASS_ERR = 0, 1, 2, 3, 4
 KINDS = {"sum_abs": 0, "mse": 1, "hits": 2, "cases": 3, "class_err": 4}
+GP_MAX_FEAT, GP_MAX_DEPTH, GP_MAX_LEN = 44, 20, 65536
 STATUS_NAMES = {0: "GP_OK", -1: "GP_E_INVAL", -2: "GP_E_NOMEM", -3: "GP_E_DEPTH",
                 -4: "GP_E_DEVICE", -5: "GP_E_AGAIN", -6: "GP_E_NOTFOUND", -7: "GP_E_TIMEOUT"}
 

@@ -92,6 +92,8 @@ int core_reg_levels(int vi) {
 // sin/cos/exp/log code, 4 trees only with it.
 static bool mode_no_transc(int mode) { return mode == 1 || mode == 2 || mode == 3; }
 
+static constexpr int kShallowDepth = 12;
+
 int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc, bool boolean, bool trees_only) {
     // Programs rich in sin/cos/exp/log (binary64, evaluated by compiled code
     // outside the core) run best with room for that code (no spills) and as
@@ -119,6 +121,8 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
         if ((v.arith == 2) != boolean) continue;
         if (v.arith >= 3 && !trees_only) continue;
         if (v.nf < n_load || v.d < depth || (mode_no_transc(v.arith) && has_transc)) continue;
+        // the deep variants (fewer waves per SIMD) serve only programs that need them
+        if (v.d > kShallowDepth && depth <= kShallowDepth) continue;
         if (best < 0) { best = i; continue; }
         const bool better = boolean ? score_bool(v) > score_bool(kCoreVariants[best])
                                     : score(v) > score(kCoreVariants[best]);
@@ -210,6 +214,19 @@ struct Emitter {
                 ((op | (fl << 4)) << 24),
             cst);
         phase = 0;   // the core is entered again after an exit
+    }
+    // protected division, in the core (every arithmetic kernel has its
+    // handlers): the exit's payload layout, without leaving
+    void div(int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
+        if (a_const && b_const) return exit(GP_PDIV, oa, ob, od, true, true, cst);
+        const int kind = a_const ? CK_DCV : b_const ? CK_DVC : CK_DVV;
+        put(kind, GP_PDIV, 0, 0,
+            (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16), cst);
+    }
+    // an operation that leaves the core, except protected division in arithmetic kernels
+    void apply(uint32_t op, bool boolean, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
+        if (op == GP_PDIV && !boolean) div(oa, ob, od, a_const, b_const, cst);
+        else exit(op, oa, ob, od, a_const, b_const, cst);
     }
 };
 
@@ -304,17 +321,19 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
             }
             continue;
         }
-        // protected division, the transcendentals and the classification functions leave the core
+        // protected division has handlers of its own; the transcendentals and the classification
+        // functions leave the core
+        const bool bl = v.arith == 2;
         switch (mode) {
-            case M_SS: e.exit(op, (h - 2) * T, (h - 1) * T, (h - 2) * T, false, false, 0); break;
-            case M_SSR: e.exit(op, (h - 1) * T, (h - 2) * T, (h - 2) * T, false, false, 0); break;
-            case M_SX: e.exit(op, (h - 1) * T, xb, (h - 1) * T, false, false, 0); break;
-            case M_XS: e.exit(op, xa, (h - 1) * T, (h - 1) * T, false, false, 0); break;
-            case M_SC: e.exit(op, (h - 1) * T, 0, (h - 1) * T, false, true, c); break;
-            case M_CS: e.exit(op, 0, (h - 1) * T, (h - 1) * T, true, false, c); break;
-            case M_XX: e.exit(op, xa, xb, h * T, false, false, 0); break;
-            case M_XC: e.exit(op, xa, 0, h * T, false, true, c); break;
-            case M_CX: e.exit(op, 0, xb, h * T, true, false, c); break;
+            case M_SS: e.apply(op, bl, (h - 2) * T, (h - 1) * T, (h - 2) * T, false, false, 0); break;
+            case M_SSR: e.apply(op, bl, (h - 1) * T, (h - 2) * T, (h - 2) * T, false, false, 0); break;
+            case M_SX: e.apply(op, bl, (h - 1) * T, xb, (h - 1) * T, false, false, 0); break;
+            case M_XS: e.apply(op, bl, xa, (h - 1) * T, (h - 1) * T, false, false, 0); break;
+            case M_SC: e.apply(op, bl, (h - 1) * T, 0, (h - 1) * T, false, true, c); break;
+            case M_CS: e.apply(op, bl, 0, (h - 1) * T, (h - 1) * T, true, false, c); break;
+            case M_XX: e.apply(op, bl, xa, xb, h * T, false, false, 0); break;
+            case M_XC: e.apply(op, bl, xa, 0, h * T, false, true, c); break;
+            case M_CX: e.apply(op, bl, 0, xb, h * T, true, false, c); break;
             case M_S: e.exit(op, (h - 1) * T, 0, (h - 1) * T, false, false, 0); break;
             case M_X: e.exit(op, xa, 0, h * T, false, false, 0); break;
             default: e.exit(op, 0, 0, h * T, true, false, c); break;  // M_C
@@ -358,9 +377,9 @@ static int translate_linear(const uint32_t* w, int64_t n, const uint32_t* cst, i
         if (!is_core_op(op, false)) {   // protected division and the classification functions
             if (c1 && c2) {
                 e.put(CK_MOVC, 0, d, 0, 0, v1);
-                e.exit(op, d * T, 0, d * T, false, true, v2);
+                e.apply(op, false, d * T, 0, d * T, false, true, v2);
             } else {
-                e.exit(op, c1 ? 0 : off(s1), c2 ? 0 : off(s2), d * T, c1, c2, c1 ? v1 : v2);
+                e.apply(op, false, c1 ? 0 : off(s1), c2 ? 0 : off(s2), d * T, c1, c2, c1 ? v1 : v2);
             }
             continue;
         }

@@ -82,6 +82,12 @@ VARIANTS = [
     (8, 6, 20, 48, 2),
     (8, 8, 20, 32, 2),
     (4, 12, 32, 40, 2),
+    # deep programs: every tree of at most GP_MAX_LEN nodes needs at most 20
+    # levels (15 without IF), 16 for the binary Boolean set; with more than 32
+    # features the deepest that fits beside them is 12
+    (4, 20, 32, 40, 0),
+    (4, 12, 44, 32, 4),
+    (4, 16, 32, 40, 2),
 ]
 
 
@@ -116,7 +122,14 @@ def reg_levels(D, mode):
 
 # handler kinds (keep in sync with the generated enum below)
 KINDS = ["EXIT", "SS", "SSR", "SX", "XS", "SC", "CS", "XX", "XX2", "XC", "CX", "PUSHX", "PUSHC",
-         "RR", "XR", "FF", "CR", "RC", "MOVC", "MOVX"]
+         "RR", "XR", "FF", "CR", "RC", "MOVC", "MOVX", "DVV", "DVC", "DCV"]
+# Protected division runs in the core: a / b with a and b at any two offsets
+# (DVV), b the constant (DVC) or a the constant (DCV), the result to a third
+# offset.  Its temporaries are the last DIV_TMP registers of the compiler's
+# range (clobbered by the block), its flags vcc, its indexes s73/s74/s79 and
+# the protection threshold s80.
+DIV_TMP = 7
+DIV_THRESHOLD = 0x358637BD       # 1e-6f: |b| below it gives 1
 K = {k: i for i, k in enumerate(KINDS)}
 
 
@@ -125,10 +138,17 @@ def vr(n):
     return "v%d" % n
 
 
+VOP3_ONLY = ("v_bitop3", "v_div_scale_f32", "v_fma_f32", "v_div_fmas_f32", "v_div_fixup_f32")
+
+
 def insn_bytes(text):
-    """Encoded size of an instruction the handlers use: scalar loads and VOP3
-    (v_bitop3_b32) take 8 bytes, everything else 4."""
-    return 8 if text.startswith(("s_load", "v_bitop3")) else 4
+    """Encoded size of an instruction the handlers use: scalar loads, VOP3
+    encodings and a scalar move of a literal take 8 bytes, everything else 4."""
+    if text.startswith(("s_load",) + VOP3_ONLY) or text.split(" ")[0].endswith("_e64"):
+        return 8
+    if text.startswith("s_mov_b32") and "0x" in text:
+        return 8
+    return 4
 
 
 class Handler:
@@ -136,6 +156,7 @@ class Handler:
         self.kind, self.op, self.p1, self.p2 = kind, op, p1, p2
         self.lines = []
         self.size = 0
+        self.phases = None      # (phase A lines, phase B lines) of a handler written per phase
 
     def emit(self, text, nbytes):
         self.lines.append(text)
@@ -289,6 +310,9 @@ def gen_variant(T, D, NF, NCV, mode=0):
     epilogue(h)
     hs.append(h)
 
+    for kind in ("DVV", "DVC", "DCV"):
+        hs.append(div_handler(kind, T, V0))
+
     if mode >= 3:                      # trees only: no linear handlers
         return finish(hs, tag, V0, FO)
 
@@ -355,6 +379,67 @@ def gen_variant(T, D, NF, NCV, mode=0):
         hs.append(h)
 
     return finish(hs, tag, V0, FO)
+
+
+def div_handler(kind, T, V0):
+    """Protected division in the core: d = |b| < 1e-6f ? 1 : a / b for the
+    T slots, a and b at offsets (or the constant), d at a third offset, all
+    in the exit's payload layout (byte 0 a, byte 1 b, byte 2 d).
+
+    The quotient is the correctly rounded IEEE one, by the sequence the
+    compiler emits for a binary32 division with denormals kept: scale
+    operands (v_div_scale), reciprocal, two Newton-Raphson refinements of it
+    and of the quotient with fused multiply-adds, the scaled fused add
+    (v_div_fmas, whose scale flag is vcc) and the special-case fix-up
+    (v_div_fixup).  Its dependent reads keep the compiler's spacing: one
+    instruction between the reciprocal and its first use, six between the
+    vcc write and v_div_fmas.  Operands are copied out of the index range
+    slot by slot (the index mode offsets every VGPR of the enabled fields,
+    so the arithmetic runs with it off), and the select writes the result
+    through the destination index."""
+    a_const, b_const = kind == "DCV", kind == "DVC"
+    tA, tB, tD, tR, tN, tE, tF = (vr(V0 - DIV_TMP + k) for k in range(DIV_TMP))
+
+    def body(A, B, Dx, C):
+        L = ["s_mov_b32 s80, 0x%x" % DIV_THRESHOLD]
+        if a_const or b_const:
+            L.append("s_set_gpr_idx_off")
+            L.append("v_mov_b32_e32 %s, %s" % (tA if a_const else tB, C))
+        for j in range(T):
+            if not a_const:
+                L.append("s_set_gpr_idx_on %s, gpr_idx(SRC0)" % A)
+                L.append("v_mov_b32_e32 %s, %s" % (tA, vr(V0 + j)))
+            if not b_const:
+                L.append("s_set_gpr_idx_on %s, gpr_idx(SRC0)" % B)
+                L.append("v_mov_b32_e32 %s, %s" % (tB, vr(V0 + j)))
+            L.append("s_set_gpr_idx_off")
+            L += ["v_div_scale_f32 %s, vcc, %s, %s, %s" % (tD, tB, tB, tA),
+                  "v_rcp_f32_e32 %s, %s" % (tR, tD),
+                  "v_div_scale_f32 %s, vcc, %s, %s, %s" % (tN, tA, tB, tA),
+                  "v_fma_f32 %s, -%s, %s, 1.0" % (tE, tD, tR),
+                  "v_fmac_f32_e32 %s, %s, %s" % (tR, tE, tR),
+                  "v_mul_f32_e32 %s, %s, %s" % (tE, tN, tR),
+                  "v_fma_f32 %s, -%s, %s, %s" % (tF, tD, tE, tN),
+                  "v_fmac_f32_e32 %s, %s, %s" % (tE, tF, tR),
+                  "v_fma_f32 %s, -%s, %s, %s" % (tD, tD, tE, tN),
+                  "v_div_fmas_f32 %s, %s, %s, %s" % (tD, tD, tR, tE),
+                  "v_div_fixup_f32 %s, %s, %s, %s" % (tD, tD, tB, tA),
+                  # vcc = |b| >= 1e-6f or b is NaN: keep the quotient, else 1
+                  "v_cmp_nlt_f32_e64 vcc, |%s|, s80" % tB,
+                  "s_set_gpr_idx_on %s, gpr_idx(DST)" % Dx,
+                  "v_cndmask_b32_e32 %s, 1.0, %s, vcc" % (vr(V0 + j), tD)]
+        return L
+
+    h = Handler(K[kind], 3)
+    # phase A: own record in s[64:67], the next one already in s[68:71]
+    la = ["s_lshr_b32 s74, s66, 8", "s_lshr_b32 s79, s66, 16"] + body("s66", "s74", "s79", "s67")
+    la += ["s_add_u32 s62, s62, 16", "s_setpc_b64 s[68:69]"]
+    # phase B: own record in s[68:71], saved before the load of the next two
+    lb = ["s_mov_b32 s73, s70", "s_lshr_b32 s74, s70, 8", "s_lshr_b32 s79, s70, 16", "s_mov_b32 s72, s71",
+          "s_add_u32 s62, s62, 16", "s_load_dwordx8 s[64:71], s[60:61], s62"] + body("s73", "s74", "s79", "s72")
+    lb += ["s_waitcnt lgkmcnt(0)", "s_setpc_b64 s[64:65]"]
+    h.phases = (la, lb)
+    return h
 
 
 def bool_handlers(hs, T, D, V0, FO, prologue, idx_on, epilogue, valu):
@@ -431,6 +516,10 @@ def _copy(h, kind):
 
 def phase_a(h, tag):
     c = _copy(h, h.kind)
+    if h.phases:
+        for x in h.phases[0]:
+            c.emit(x, insn_bytes(x))
+        return c
     if h.kind == K["EXIT"]:
         for x in h.lines:
             c.emit(x, 4)
@@ -453,6 +542,10 @@ def phase_a(h, tag):
 
 def phase_b(h, tag):
     c = _copy(h, h.kind | PHASE_B)
+    if h.phases:
+        for x in h.phases[1]:
+            c.emit(x, insn_bytes(x))
+        return c
     if h.kind == K["EXIT"]:
         c.emit("s_set_gpr_idx_off", 4)
         c.emit("s_mov_b32 s66, s70", 4)
@@ -593,6 +686,9 @@ def main(out_dir):
         seen[core] = (tag, hs, nslots)
         text = asm_text(T, D, NF, tag, hs)
         clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
+        if AR != 2:    # the division handlers' temporaries, flags, indexes and threshold
+            clob_v += ", " + ", ".join('"%s"' % vr(n) for n in range(NCV - DIV_TMP, NCV)) + ', "vcc", "s79", "s80"'
+            assert NCV - DIV_TMP >= 24
         assert NCV + FO + NF * T <= 256
         lines.append("template <> struct Core<%d, %d, %d, %d, %d> {" % (T, D, NF, NCV, core[4]))
         lines.append("    // run from byte offset `off` until an exit; returns the exit's payload and constant")

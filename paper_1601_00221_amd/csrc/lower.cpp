@@ -70,11 +70,13 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
         return GP_E_DEPTH;
     }
     const int32_t N = (int32_t)n;
-    std::vector<int32_t> kid(3 * (size_t)N, -1);
-    std::vector<int8_t> ar(N);
-    std::vector<int8_t> filled(N, 0);
-    std::vector<int32_t> open;
-    open.reserve(64);
+    // per-thread work arrays, reused from program to program (host threads lower programs in parallel)
+    thread_local std::vector<int32_t> kid, need, open;
+    thread_local std::vector<int8_t> ar, filled;
+    kid.assign(3 * (size_t)N, -1);
+    ar.resize(N);
+    filled.assign(N, 0);
+    open.clear();
     for (int32_t i = 0; i < N; i++) {
         const int op = tok[i] & 0xFF;
         const int a = arity_of(op, opset);
@@ -112,7 +114,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
     s.n_nodes = N;
 
     // Stack levels each subtree needs when its terminals are read as operands.
-    std::vector<int32_t> need(N, 0);
+    need.assign(N, 0);
     // IF: its three operands in the order they are evaluated (decreasing need, ties left to right)
     auto if_order = [&](int32_t i, int32_t ord[3]) {
         int32_t nd[3];
@@ -171,8 +173,8 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
     };
 
     struct Frame { int32_t node; int32_t stage; };
-    std::vector<Frame> fr;
-    fr.reserve(64);
+    thread_local std::vector<Frame> fr;
+    fr.clear();
     if (ar[0] == 0) {
         // A lone terminal: push it.
         push_terminal(0);

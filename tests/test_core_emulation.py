@@ -45,16 +45,25 @@ class CoreEmu:
         self.prog = {h.slot: [self._parse(x) for x in h.lines] for h in hs}
         self.v = np.zeros((256, 64), np.float32)
         self.s = [0] * 128
+        self.vcc = np.zeros(64, bool)
         self.steps = 0
 
     # ------------------------------------------------------------------ parse
     @staticmethod
     def _reg(tok):
         tok = tok.strip()
+        if tok == "vcc":
+            return ("vcc", 0)
+        if tok.startswith("-v"):
+            return ("vneg", int(tok[2:]))
+        if tok.startswith("|v"):
+            return ("vabs", int(tok[2:-1]))
         if tok.startswith("v"):
             return ("v", int(tok[1:]))
         if tok.startswith("s"):
             return ("s", int(tok[1:]))
+        if "." in tok:
+            return ("f", float(tok))
         return ("i", int(tok, 0))
 
     def _parse(self, line):
@@ -133,14 +142,29 @@ class CoreEmu:
         def src(k, a, field):
             if k == "s":
                 return np.full(64, np.frombuffer(np.uint32(self.s[a]).tobytes(), np.float32)[0])
+            if k == "f":
+                return np.full(64, np.float32(a))
             r = a + (m0 if idx_on and field in modes else 0)
             assert 0 <= r < 256
+            if k == "vneg":
+                return -self.v[r]
+            if k == "vabs":
+                return np.abs(self.v[r])
             return self.v[r]
+        if args[0][0] == "vcc":          # a compare: its destination is the flag register
+            self._div_op(op, args, None, src)
+            return
         (_, d) = args[0]
         dr = d + (m0 if idx_on and "DST" in modes else 0)
-        assert self.V0 <= dr < 256, dr
+        # the core's range, or the division handlers' temporaries below it
+        assert self.V0 - gen_core.DIV_TMP <= dr < 256, dr
+        if dr < self.V0:
+            assert not (idx_on and "DST" in modes)
         if op == "v_mov_b32_e32":
             self.v[dr] = src(*args[1], "SRC0")
+            return
+        if op in DIV_OPS:
+            self._div_op(op, args, dr, src)
             return
         if op == "v_bitop3_b32":
             # bit i of the table is the result for sources (s0, s1, s2) = bits of i, s0 the highest
@@ -169,6 +193,44 @@ class CoreEmu:
             elif op == "v_mul_f32_e32": r = a * b
             else: raise AssertionError(op)
         self.v[dr] = r.astype(np.float32)
+
+    def _div_op(self, op, args, dr, src):
+        """The instructions of the division handlers.  The scaling that
+        v_div_scale / v_div_fmas apply near the ends of the exponent range is
+        not modelled: the scale flag stays clear, and v_div_fixup gives the
+        IEEE quotient wherever an operand or the result is zero, infinite,
+        NaN or beyond 2^+-60 (where the hardware scales).  Elsewhere the
+        quotient comes out of the reciprocal and its fused refinements, so
+        operand offsets, the protection select and the destination are what
+        is checked."""
+        f64 = np.float64
+        with np.errstate(all="ignore"):
+            if op == "v_div_scale_f32":
+                self.v[dr] = src(*args[2], "SRC0")
+                self.vcc = np.zeros(64, bool)
+            elif op == "v_rcp_f32_e32":
+                self.v[dr] = (f64(1.0) / src(*args[1], "SRC0").astype(f64)).astype(np.float32)
+            elif op in ("v_fma_f32", "v_div_fmas_f32"):
+                a, b, c = src(*args[1], "SRC0"), src(*args[2], "SRC1"), src(*args[3], "SRC2")
+                if op == "v_div_fmas_f32":
+                    assert not self.vcc.any()
+                self.v[dr] = (a.astype(f64) * b.astype(f64) + c.astype(f64)).astype(np.float32)
+            elif op == "v_fmac_f32_e32":
+                a, b = src(*args[1], "SRC0"), src(*args[2], "SRC1")
+                self.v[dr] = (a.astype(f64) * b.astype(f64) + self.v[dr].astype(f64)).astype(np.float32)
+            elif op == "v_div_fixup_f32":
+                q, den, num = src(*args[1], "SRC0"), src(*args[2], "SRC1"), src(*args[3], "SRC2")
+                ieee = (num.astype(f64) / den.astype(f64)).astype(np.float32)
+                big = lambda x: ~np.isfinite(x) | (x == 0) | (np.abs(x) > 2.0 ** 60) | (np.abs(x) < 2.0 ** -60)
+                self.v[dr] = np.where(big(num) | big(den) | big(q), ieee, q)
+            elif op == "v_cmp_nlt_f32_e64":
+                a, b = src(*args[1], "SRC0"), src(*args[2], "SRC1")
+                self.vcc = ~(a < b)
+            elif op == "v_cndmask_b32_e32":
+                a, b = src(*args[1], "SRC0"), src(*args[2], "SRC1")
+                self.v[dr] = np.where(self.vcc, b, a)
+            else:
+                raise AssertionError(op)
 
     # ------------------------------------------------------------------ kernel side
     def gather(self, off):
@@ -228,6 +290,10 @@ class CoreEmu:
         return out
 
 
+DIV_OPS = ("v_div_scale_f32", "v_rcp_f32_e32", "v_fma_f32", "v_div_fmas_f32", "v_fmac_f32_e32", "v_div_fixup_f32",
+           "v_cmp_nlt_f32_e64", "v_cndmask_b32_e32")
+
+
 def _same(a, b):
     return (a.view(np.int32) == b.view(np.int32)) | (np.isnan(a) & np.isnan(b))
 
@@ -277,6 +343,61 @@ def test_core_classification_match_oracle(vi):
     got = emu.evaluate(words, prog_off, X, F)
     ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
     assert _same(got, ref).all()
+
+
+@pytest.mark.parametrize("vi", [0] + [i for i, v in enumerate(gen_core.VARIANTS) if v[4] in (1, 3, 4)][:3])
+def test_core_division_forms(vi):
+    """Protected division runs in the core in every operand form: stack and
+    stack in both orders, stack and variable, variable and stack, constants
+    on either side, two variables, a variable and a constant, and the
+    register forms; divisors below 1e-6 in magnitude (and zeros of both
+    signs) give 1.  Every division handler is run, and the results are the
+    oracle's bits."""
+    T, D, NF, NCV, mode = gen_core.VARIANTS[vi]
+    F = 3
+    exprs = ["(/ x0 x1)", "(/ x1 x0)", "(/ (+ x0 x2) (* x1 x2))", "(/ (* x1 x2) (+ x0 x2))",
+             "(/ (+ x0 x1) x2)", "(/ x2 (+ x0 x1))", "(/ (+ x0 x1) 0.37)", "(/ -2.5 (+ x0 x1))",
+             "(/ x0 1e-7)", "(/ 3 x1)", "(/ x1 -0.0)", "(/ (/ x0 x1) (/ x2 (/ x1 x0)))",
+             "(+ x0 (/ (- x1 x2) (* (+ x0 x0) (/ 1.5 x2))))"]
+    from tests import progs
+    pop = progs.pop(*exprs)
+    rng = synth.rng_for(77)
+    X = synth.uniform_cases(rng, F, 64 * T + 29, -3, 3)
+    X[:, ::5] = 0.0
+    X[1, 1::7] = -0.0
+    X[1, 2::7] = 5e-7
+    X[2, 3::11] = -9.9e-7
+    X[0, 4::13] = 3.0e38
+    emu = CoreEmu(vi)
+
+    def handler_kinds(words):
+        rec = words.reshape(-1, 4)
+        out = []
+        for r in rec:
+            a = int(r[0]) | (int(r[1]) << 32)
+            slot = (a - BASE) // gen_core.SLOT
+            if a >= BASE and slot in emu.by_slot:
+                out.append((emu.by_slot[slot].kind & 0x7F, int(r[2])))
+        return out
+
+    words, prog_off = gp.core_lower(pop, F, vi, BASE)
+    got = emu.evaluate(words, prog_off, X, F)
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    assert _same(got, ref).all(), np.argwhere(~_same(got, ref))[:4]
+    hk = handler_kinds(words)
+    for k in ("DVV", "DVC", "DCV"):
+        assert any(kind == gen_core.K[k] for kind, _ in hk), k
+    # no division leaves the core
+    assert not any(kind == gen_core.K["EXIT"] and (pay >> 24) & 15 == synth.PDIV for kind, pay in hk)
+    if mode in (0, 1):
+        lp = synth.linear_population(rng, 12, 4, 40, (synth.PDIV, synth.ADD, synth.PDIV), 8, F, n_const=3,
+                                     crange=(-2.0, 2.0))
+        words, prog_off = gp.core_lower(lp, F, vi, BASE)
+        got = emu.evaluate(words, prog_off, X, F)
+        ref = oracle.linear_outputs(lp.code, lp.off, lp.cst, lp.cst_off, lp.n_reg, X)
+        assert _same(got, ref).all()
+        hk = handler_kinds(words)
+        assert not any(kind == gen_core.K["EXIT"] and (pay >> 24) & 15 == synth.PDIV for kind, pay in hk)
 
 
 @pytest.mark.parametrize("vi", LINEAR)

@@ -162,16 +162,81 @@ def test_comb_lowers_to_depth_one():
     assert st["max_depth"] == 1 and st["n_instr"] == 127
 
 
-def test_balanced_tree_hits_depth_limit():
-    def full(d):
-        return "x0" if d == 0 else "(+ %s %s)" % (full(d - 1), full(d - 1))
-    tok, cst = progs.parse(full(12))      # 4096 leaves, needs 12 levels
+def test_deepest_trees_lower():
+    """The largest full binary tree within GP_MAX_LEN needs 15 levels; an
+    IF-rich tree of 59,050 nodes needs 20, the limit, so every valid tree
+    lowers (no depth rejection below GP_MAX_LEN nodes)."""
+    from tests import deeptrees
+    t = deeptrees.Tree(synth.rng_for(3), 1)
+    t.full(15)
+    tok, cst = t.lists()
+    assert len(tok) == 65535
     _, st = gp.gp_lower_tree(tok, cst, 1)
-    assert st["max_depth"] == 12
-    tok, cst = progs.parse(full(13))      # needs 13 levels
-    with pytest.raises(gp.GPError) as e:
-        gp.gp_lower_tree(tok, cst, 1)
-    assert e.value.status == gp.GP_E_DEPTH
+    assert st["max_depth"] == 15
+    tok, cst = deeptrees.need20(synth.rng_for(4), 3)
+    assert len(tok) == 59050
+    _, st = gp.gp_lower_tree(tok, cst, 3)
+    assert st["max_depth"] == gp.GP_MAX_DEPTH == 20
+    t = deeptrees.Tree(synth.rng_for(5), 2)
+    t.full_if(6)                          # 1,093 nodes, 13 levels
+    tok, cst = t.lists()
+    _, st = gp.gp_lower_tree(tok, cst, 2)
+    assert (len(tok), st["max_depth"]) == (1093, 13)
+
+
+def test_smallest_tree_per_depth_brute_force():
+    """The growth that bounds the depth at 20: the fewest nodes of a tree
+    needing k levels, by exhaustive search over shapes up to 28 nodes (with
+    unary, binary and IF functions), equals the recurrence
+    m(k) = min(2 m(k-1) + 1, 3 m(k-2) + 1) that the deep trees follow."""
+    from functools import lru_cache
+    import itertools
+
+    @lru_cache(None)
+    def needs(n):
+        """Set of (need, is_terminal) reachable by trees of exactly n nodes."""
+        if n == 1:
+            return frozenset({(1, True)})
+        r = set()
+        for a in needs(n - 1):                 # unary
+            r.add((a[0], False))
+        for k in range(1, n - 1):              # binary: k + (n-1-k) nodes
+            for a in needs(k):
+                for b in needs(n - 1 - k):
+                    if a[1] and b[1]:
+                        r.add((1, False))
+                    elif b[1]:
+                        r.add((a[0], False))
+                    elif a[1]:
+                        r.add((b[0], False))
+                    else:
+                        r.add((max(a[0], b[0]) if a[0] != b[0] else a[0] + 1, False))
+        for i in range(1, n - 2):              # IF: three operands
+            for j in range(1, n - 1 - i):
+                k = n - 1 - i - j
+                if k < 1:
+                    continue
+                for a, b, c in itertools.product(needs(i), needs(j), needs(k)):
+                    nd = sorted([a[0], b[0], c[0]], reverse=True)
+                    r.add((max(nd[0], nd[1] + 1, nd[2] + 2), False))
+        return frozenset(r)
+
+    exact = {}
+    for n in range(1, 29):
+        for d, term in needs(n):
+            if not term:
+                exact.setdefault(d, n)
+    fewest = {k: min(n for d, n in exact.items() if d >= k) for k in exact}   # needing at least k
+    m = {1: 2, 2: 4, 3: 4}
+    for k in range(4, 22):
+        m[k] = min(2 * m[k - 1] + 1, 3 * m[k - 2] + 1)
+    assert len(fewest) == 6 and all(fewest[k] == m[k] for k in fewest), (fewest, m)
+    assert m[20] <= 65536 < m[21]
+    import re
+    hdr = open(gp.HEADER).read()
+    for name in ("GP_MAX_DEPTH", "GP_MAX_LEN", "GP_MAX_FEAT"):
+        assert int(re.search(r"#define %s (\d+)" % name, hdr).group(1)) == getattr(gp, name)
+    assert m[gp.GP_MAX_DEPTH] <= gp.GP_MAX_LEN < m[gp.GP_MAX_DEPTH + 1]
 
 
 @pytest.mark.parametrize("tok", [
