@@ -58,6 +58,22 @@ static uint32_t fbits(float f) {
     return u;
 }
 
+namespace {
+struct LowerFrame {
+    int32_t node;
+    int32_t stage;
+};
+struct LowerScratch {
+    std::vector<int32_t> kid, need, open;
+    std::vector<int8_t> ar, filled;
+    std::vector<LowerFrame> fr;
+};
+LowerScratch& lower_scratch() {
+    thread_local LowerScratch s;
+    return s;
+}
+}  // namespace
+
 int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, uint32_t* out,
                TreeLowering* st, char* err, int opset) {
     TreeLowering s;
@@ -71,8 +87,10 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
     }
     const int32_t N = (int32_t)n;
     // per-thread work arrays, reused from program to program (host threads lower programs in parallel)
-    thread_local std::vector<int32_t> kid, need, open;
-    thread_local std::vector<int8_t> ar, filled;
+    LowerScratch& S = lower_scratch();
+    std::vector<int32_t>&kid = S.kid, &need = S.need, &open = S.open;
+    std::vector<int8_t>&ar = S.ar, &filled = S.filled;
+    std::vector<LowerFrame>& fr = S.fr;
     kid.assign(3 * (size_t)N, -1);
     ar.resize(N);
     filled.assign(N, 0);
@@ -172,17 +190,15 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
         else emit(OP_PUSH, M_C, 0, 0, cst[i], +1, 0, false, 0);
     };
 
-    struct Frame { int32_t node; int32_t stage; };
-    thread_local std::vector<Frame> fr;
     fr.clear();
     if (ar[0] == 0) {
         // A lone terminal: push it.
         push_terminal(0);
     } else {
-        fr.push_back({0, 0});
+        fr.push_back(LowerFrame{0, 0});
     }
     while (!fr.empty()) {
-        Frame& f = fr.back();
+        LowerFrame& f = fr.back();
         const int32_t i = f.node;
         const int op = tok[i] & 0xFF;
         const int32_t a = kid[3 * (size_t)i];
@@ -193,7 +209,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
                 const int32_t c = kid[3 * (size_t)i + ord[f.stage]];
                 f.stage++;
                 if (ar[c] == 0) push_terminal(c);
-                else fr.push_back({c, 0});
+                else fr.push_back(LowerFrame{c, 0});
                 continue;
             }
             // operand ord[k] is the k-th of the three values from the bottom
@@ -210,7 +226,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
                 fr.pop_back();
             } else if (f.stage == 0) {
                 f.stage = 1;
-                fr.push_back({a, 0});
+                fr.push_back(LowerFrame{a, 0});
             } else {
                 emit(op, M_S, 0, 0, 0.0f, 0, 1, true, 1);
                 fr.pop_back();
@@ -232,7 +248,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
         } else if (tb) {
             if (f.stage == 0) {
                 f.stage = 1;
-                fr.push_back({a, 0});
+                fr.push_back(LowerFrame{a, 0});
             } else {
                 if (is_var(b)) emit(op, M_SX, 0, feat(b), 0.0f, 0, 1, true, 2);
                 else emit(op, M_SC, 0, 0, cst[b], 0, 1, true, 2);
@@ -241,7 +257,7 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
         } else if (ta) {
             if (f.stage == 0) {
                 f.stage = 1;
-                fr.push_back({b, 0});
+                fr.push_back(LowerFrame{b, 0});
             } else {
                 if (is_var(a)) emit(op, M_XS, feat(a), 0, 0.0f, 0, 1, true, 2);
                 else emit(op, M_CS, 0, 0, cst[a], 0, 1, true, 2);
@@ -251,10 +267,10 @@ int lower_tree(const int32_t* tok, const float* cst, int64_t n, int32_t n_feat, 
             const bool left_first = need[a] >= need[b];
             if (f.stage == 0) {
                 f.stage = 1;
-                fr.push_back({left_first ? a : b, 0});
+                fr.push_back(LowerFrame{left_first ? a : b, 0});
             } else if (f.stage == 1) {
                 f.stage = 2;
-                fr.push_back({left_first ? b : a, 0});
+                fr.push_back(LowerFrame{left_first ? b : a, 0});
             } else {
                 const bool rev = !left_first && !commutative(op);
                 if (rev) s.n_reversed++;
