@@ -468,8 +468,8 @@ def bench_served(args):
     total_gpop = sum(g for lst in reqs for _, g in lst)
     n_warm = max(0, min(args.warmup, args.requests - 1))
 
-    def run_mode(batching):
-        srv = gp.Server(batching=batching)
+    def run_mode(batching, budget=0):
+        srv = gp.Server(batching=batching, memory_budget=budget)
         ids = [srv.add_dataset(X, y) for X, y in data]
         lat = []
         gpop_meas = [0]
@@ -607,6 +607,24 @@ def bench_served(args):
                                               for k in ob_res) and
                                           all(torch.equal(ob_res[k].view(torch.int32), res_b[k].view(torch.int32))
                                               for k in ob_res)}
+    admission = None
+    if args.budget_frac > 0:
+        # device bytes a request holds while in flight (the server's own estimate, restated): core code,
+        # program records and groups, fp64 partial sums per 256-case block, units
+        def req_bytes(pop, N):
+            n_instr = int(pop.sizes().sum()) + pop.n_prog
+            return 16 * n_instr + 40 * pop.n_prog + 8 * pop.n_prog * ((N + 255) // 256) + 4096
+        per_run = [max(req_bytes(pop, w.runs[ri].X.shape[1]) for pop, _ in reqs[ri]) for ri in range(len(w.runs))]
+        working_set = sum(per_run)
+        budget = int(max(args.budget_frac * working_set, 1.25 * max(per_run)))
+        log("admission: budget %.1f MB = %.0f %% of the %.1f MB working set (every run's largest request in flight)"
+            % (budget / 1e6, 100 * budget / working_set, working_set / 1e6))
+        adm, res_a = run_mode(True, budget)
+        log("served under the budget", adm)
+        admission = dict(adm, budget_bytes=budget, working_set_bytes=working_set,
+                         budget_fraction=budget / working_set,
+                         fitness_identical=all(torch.equal(res_a[k].view(torch.int32), res_b[k].view(torch.int32))
+                                               for k in res_a))
     config = {"workload": w.name, "n_runs": len(w.runs), "requests_per_run": args.requests,
               "warmup_requests_per_run": n_warm, "gpop_total": total_gpop, "fitness": "mse",
               "arrivals": "closed loop, Exp(2 ms) think time"}
@@ -617,6 +635,8 @@ def bench_served(args):
                             fitness_identical=same)
     if open_loop is not None:
         res["open_loop"] = open_loop
+    if admission is not None:
+        res["admission"] = admission
     # kernel time over all batched launches of the served run (warm-up included)
     all_gpop = total_gpop
     res["roofline"] = roofline(all_gpop / max(n_launch, 1), kernel_ms / 1e3 / max(n_launch, 1), "k_core", w.name)
@@ -836,6 +856,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-arith", action="store_true", help="scale-tree: skip the {+,-,*} sub-measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--budget-frac", type=float, default=0.0,
+                    help="served: also run under a device-memory budget of this fraction of the working set")
     ap.add_argument("--requests", type=int, default=10, help="served: requests per run")
     ap.add_argument("--open-load", type=float, default=0.0,
                     help="served: also run an open loop at this fraction of the closed loop's served rate")

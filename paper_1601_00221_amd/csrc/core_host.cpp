@@ -223,9 +223,19 @@ struct Emitter {
         put(kind, GP_PDIV, 0, 0,
             (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16), cst);
     }
-    // an operation that leaves the core, except protected division in arithmetic kernels
+    // >, <, ==, logical AND and OR in the core: 1 or 0 per slot
+    void cmp(uint32_t op, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
+        if (a_const && b_const) return exit(op, oa, ob, od, true, true, cst);
+        const int kind = a_const ? CK_CCV : b_const ? CK_CVC : CK_CVV;
+        put(kind, (int)op, 0, 0,
+            (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16), cst);
+    }
+    // the binary functions the arithmetic kernels apply in their own handlers (protected division and the
+    // classification functions); sin/cos/exp/log leave the core
     void apply(uint32_t op, bool boolean, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
-        if (op == GP_PDIV && !boolean) div(oa, ob, od, a_const, b_const, cst);
+        if (!boolean && op == GP_PDIV) div(oa, ob, od, a_const, b_const, cst);
+        else if (!boolean && (op == GP_GT || op == GP_LT || op == GP_EQ || op == GP_AND || op == GP_OR))
+            cmp(op, oa, ob, od, a_const, b_const, cst);
         else exit(op, oa, ob, od, a_const, b_const, cst);
     }
 };
@@ -277,7 +287,11 @@ static int translate_tree(const uint32_t* w, int64_t n_instr, int vi, const Vari
                 snprintf(err, 256, "malformed three-operand instruction");
                 return GP_E_INVAL;
             }
-            e.exit(OP_IF, (h - 3 + fa) * T, (h - 3 + fb) * T, (h - 3 + pc) * T, false, false, 0);
+            // IF runs in the core: operands at three offsets, the result to the lowest, s[h-3]
+            e.put(CK_IF3, GP_IF, 0, 0,
+                  (uint32_t)((h - 3 + fa) * T) | ((uint32_t)((h - 3 + fb) * T) << 8) |
+                      ((uint32_t)((h - 3 + pc) * T) << 16) | ((uint32_t)((h - 3) * T) << 24),
+                  0);
             continue;
         }
         if (is_core_op(op, v.arith == 2)) {

@@ -122,7 +122,7 @@ def reg_levels(D, mode):
 
 # handler kinds (keep in sync with the generated enum below)
 KINDS = ["EXIT", "SS", "SSR", "SX", "XS", "SC", "CS", "XX", "XX2", "XC", "CX", "PUSHX", "PUSHC",
-         "RR", "XR", "FF", "CR", "RC", "MOVC", "MOVX", "DVV", "DVC", "DCV"]
+         "RR", "XR", "FF", "CR", "RC", "MOVC", "MOVX", "DVV", "DVC", "DCV", "CVV", "CVC", "CCV", "IF3"]
 # Protected division runs in the core: a / b with a and b at any two offsets
 # (DVV), b the constant (DVC) or a the constant (DCV), the result to a third
 # offset.  Its temporaries are the last DIV_TMP registers of the compiler's
@@ -312,6 +312,10 @@ def gen_variant(T, D, NF, NCV, mode=0):
 
     for kind in ("DVV", "DVC", "DCV"):
         hs.append(div_handler(kind, T, V0))
+    for op in list(CMP_OPS) + list(LOGIC_OPS):
+        for kind in ("CVV", "CVC", "CCV"):
+            hs.append(cmp_handler(kind, op, T, V0))
+    hs.append(if_handler(T, V0))
 
     if mode >= 3:                      # trees only: no linear handlers
         return finish(hs, tag, V0, FO)
@@ -393,7 +397,8 @@ def div_handler(kind, T, V0):
     (v_div_fmas, whose scale flag is vcc) and the special-case fix-up
     (v_div_fixup).  Its dependent reads keep the compiler's spacing: one
     instruction between the reciprocal and its first use, six between the
-    vcc write and v_div_fmas.  Operands are copied out of the index range
+    vcc write and v_div_fmas, two wait states between the compare's vcc
+    write and the select that reads it.  Operands are copied out of the index range
     slot by slot (the index mode offsets every VGPR of the enabled fields,
     so the arithmetic runs with it off), and the select writes the result
     through the destination index."""
@@ -426,6 +431,8 @@ def div_handler(kind, T, V0):
                   "v_div_fixup_f32 %s, %s, %s, %s" % (tD, tD, tB, tA),
                   # vcc = |b| >= 1e-6f or b is NaN: keep the quotient, else 1
                   "v_cmp_nlt_f32_e64 vcc, |%s|, s80" % tB,
+                  # a vector write of a mask register is read as a lane mask two wait states later at the earliest
+                  "s_nop 1",
                   "s_set_gpr_idx_on %s, gpr_idx(DST)" % Dx,
                   "v_cndmask_b32_e32 %s, 1.0, %s, vcc" % (vr(V0 + j), tD)]
         return L
@@ -440,6 +447,103 @@ def div_handler(kind, T, V0):
     lb += ["s_waitcnt lgkmcnt(0)", "s_setpc_b64 s[64:65]"]
     h.phases = (la, lb)
     return h
+
+
+# The classification functions in the core: >, <, == give 1 or 0 (an ordered
+# compare: false with a NaN); AND and OR test operands for != 0 (a NaN is
+# non-zero); IF(a, b, c) = a != 0 ? b : c.  Operand ids as the tree opcodes.
+CMP_OPS = {12: "gt", 13: "lt", 14: "eq"}
+CMP_SWAP = {"gt": "lt", "lt": "gt", "eq": "eq"}      # c op x  ==  x swap(op) c
+LOGIC_OPS = {8: "s_and_b64", 9: "s_or_b64"}
+IF_KIND = "IF3"
+
+
+def phases_of(h, body, n_idx):
+    """Both phases of a handler whose body takes its index registers (A, B,
+    D[, C]) and the constant register.  Phase A finds its record in s[64:67]
+    (the next one is already in s[68:71]); phase B saves what it needs from
+    s[68:71] before loading the next two records over s[64:71]."""
+    if n_idx == 3:
+        la = ["s_lshr_b32 s74, s66, 8", "s_lshr_b32 s79, s66, 16"] + body("s66", "s74", "s79", "s67", None)
+        lb = ["s_mov_b32 s73, s70", "s_lshr_b32 s74, s70, 8", "s_lshr_b32 s79, s70, 16", "s_mov_b32 s72, s71"]
+        regs_b = ("s73", "s74", "s79", "s72", None)
+    else:
+        la = ["s_lshr_b32 s74, s66, 8", "s_lshr_b32 s73, s66, 16", "s_lshr_b32 s79, s66, 24"] + \
+            body("s66", "s74", "s79", None, "s73")
+        lb = ["s_mov_b32 s73, s70", "s_lshr_b32 s74, s70, 8", "s_lshr_b32 s72, s70, 16", "s_lshr_b32 s79, s70, 24"]
+        regs_b = ("s73", "s74", "s79", None, "s72")
+    la += ["s_add_u32 s62, s62, 16", "s_setpc_b64 s[68:69]"]
+    lb += ["s_add_u32 s62, s62, 16", "s_load_dwordx8 s[64:71], s[60:61], s62"] + body(*regs_b)
+    lb += ["s_waitcnt lgkmcnt(0)", "s_setpc_b64 s[64:65]"]
+    h.phases = (la, lb)
+    return h
+
+
+def cmp_handler(kind, op, T, V0):
+    """d = a op b for op in >, <, ==, AND, OR (1 or 0 per slot), a and b at
+    two offsets (CVV) or one of them the record's constant (CVC: b, CCV: a),
+    d at a third; the payload is the exit's layout.  A compare writes vcc
+    (AND and OR first write the first operand's test to s[80:81] and combine
+    them); a select through the destination index writes the result, two wait
+    states after the mask is written."""
+    a_const, b_const = kind == "CCV", kind == "CVC"
+    tB = vr(V0 - DIV_TMP)
+    name = CMP_OPS.get(op)
+
+    def body(A, B, Dx, C, _):
+        L = []
+        if name is None and (a_const or b_const):
+            # the constant's truth is the same in every lane
+            L += ["v_cmp_neq_f32_e64 s[80:81], 0, %s" % C]
+        for j in range(T):
+            if name is not None:
+                if a_const:          # c op b
+                    L += ["s_set_gpr_idx_on %s, gpr_idx(SRC1)" % B,
+                          "v_cmp_%s_f32_e32 vcc, %s, %s" % (name, C, vr(V0 + j))]
+                elif b_const:        # a op c  ==  c swap(op) a
+                    L += ["s_set_gpr_idx_on %s, gpr_idx(SRC1)" % A,
+                          "v_cmp_%s_f32_e32 vcc, %s, %s" % (CMP_SWAP[name], C, vr(V0 + j))]
+                else:                # b copied out, a through the index
+                    L += ["s_set_gpr_idx_on %s, gpr_idx(SRC0)" % B,
+                          "v_mov_b32_e32 %s, %s" % (tB, vr(V0 + j)),
+                          "s_set_gpr_idx_on %s, gpr_idx(SRC0)" % A,
+                          "v_cmp_%s_f32_e32 vcc, %s, %s" % (name, vr(V0 + j), tB)]
+            else:
+                if not (a_const or b_const):
+                    L += ["s_set_gpr_idx_on %s, gpr_idx(SRC1)" % A,
+                          "v_cmp_neq_f32_e64 s[80:81], 0, %s" % vr(V0 + j)]
+                L += ["s_set_gpr_idx_on %s, gpr_idx(SRC1)" % (A if b_const else B),
+                      "v_cmp_neq_f32_e32 vcc, 0, %s" % vr(V0 + j),
+                      "s_nop 1",
+                      "%s vcc, vcc, s[80:81]" % LOGIC_OPS[op]]
+            L += ["s_nop 1",
+                  "s_set_gpr_idx_on %s, gpr_idx(DST)" % Dx,
+                  "v_cndmask_b32_e64 %s, 0, 1.0, vcc" % vr(V0 + j)]
+        return L
+
+    return phases_of(Handler(K[kind], op), body, 3)
+
+
+def if_handler(T, V0):
+    """IF(a, b, c) = a != 0 ? b : c (a NaN is non-zero) over three offsets,
+    the result to a fourth (payload bytes 0-3: a, b, c, d)."""
+    tB, tC = vr(V0 - DIV_TMP), vr(V0 - DIV_TMP + 1)
+
+    def body(A, B, Dx, _, Cx):
+        L = []
+        for j in range(T):
+            L += ["s_set_gpr_idx_on %s, gpr_idx(SRC0)" % B,
+                  "v_mov_b32_e32 %s, %s" % (tB, vr(V0 + j)),
+                  "s_set_gpr_idx_on %s, gpr_idx(SRC0)" % Cx,
+                  "v_mov_b32_e32 %s, %s" % (tC, vr(V0 + j)),
+                  "s_set_gpr_idx_on %s, gpr_idx(SRC1)" % A,
+                  "v_cmp_neq_f32_e32 vcc, 0, %s" % vr(V0 + j),
+                  "s_nop 1",
+                  "s_set_gpr_idx_on %s, gpr_idx(DST)" % Dx,
+                  "v_cndmask_b32_e32 %s, %s, %s, vcc" % (vr(V0 + j), tC, tB)]
+        return L
+
+    return phases_of(Handler(K[IF_KIND], 15), body, 4)
 
 
 def bool_handlers(hs, T, D, V0, FO, prologue, idx_on, epilogue, valu):
@@ -686,8 +790,9 @@ def main(out_dir):
         seen[core] = (tag, hs, nslots)
         text = asm_text(T, D, NF, tag, hs)
         clob_v = ", ".join('"%s"' % vr(n) for n in range(NCV, NCV + FO + NF * T))
-        if AR != 2:    # the division handlers' temporaries, flags, indexes and threshold
-            clob_v += ", " + ", ".join('"%s"' % vr(n) for n in range(NCV - DIV_TMP, NCV)) + ', "vcc", "s79", "s80"'
+        if AR != 2:    # the division and classification handlers' temporaries, flags, indexes and threshold
+            clob_v += ", " + ", ".join('"%s"' % vr(n) for n in range(NCV - DIV_TMP, NCV)) + \
+                ', "vcc", "s79", "s80", "s81"'
             assert NCV - DIV_TMP >= 24
         assert NCV + FO + NF * T <= 256
         lines.append("template <> struct Core<%d, %d, %d, %d, %d> {" % (T, D, NF, NCV, core[4]))

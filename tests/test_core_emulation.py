@@ -46,6 +46,7 @@ class CoreEmu:
         self.v = np.zeros((256, 64), np.float32)
         self.s = [0] * 128
         self.vcc = np.zeros(64, bool)
+        self.smask = np.zeros(64, bool)
         self.steps = 0
 
     # ------------------------------------------------------------------ parse
@@ -54,6 +55,8 @@ class CoreEmu:
         tok = tok.strip()
         if tok == "vcc":
             return ("vcc", 0)
+        if tok.startswith("s["):
+            return ("sp", int(tok[2:].split(":")[0]))
         if tok.startswith("-v"):
             return ("vneg", int(tok[2:]))
         if tok.startswith("|v"):
@@ -133,6 +136,9 @@ class CoreEmu:
                 elif op == "s_lshr_b32":
                     (_, d), (_, a), (_, b) = ins[1]
                     s[d] = s[a] >> b
+                elif op in ("s_and_b64", "s_or_b64"):
+                    assert [a[0] for a in ins[1]] == ["vcc", "vcc", "sp"], ins
+                    self.vcc = (self.vcc & self.smask) if op == "s_and_b64" else (self.vcc | self.smask)
                 else:
                     self._valu(op, ins[1], idx_on, m0, modes)
             else:
@@ -142,7 +148,7 @@ class CoreEmu:
         def src(k, a, field):
             if k == "s":
                 return np.full(64, np.frombuffer(np.uint32(self.s[a]).tobytes(), np.float32)[0])
-            if k == "f":
+            if k in ("f", "i"):
                 return np.full(64, np.float32(a))
             r = a + (m0 if idx_on and field in modes else 0)
             assert 0 <= r < 256
@@ -151,8 +157,8 @@ class CoreEmu:
             if k == "vabs":
                 return np.abs(self.v[r])
             return self.v[r]
-        if args[0][0] == "vcc":          # a compare: its destination is the flag register
-            self._div_op(op, args, None, src)
+        if args[0][0] in ("vcc", "sp"):   # a compare: its destination is a mask register
+            self._div_op(op, args, args[0][0], src)
             return
         (_, d) = args[0]
         dr = d + (m0 if idx_on and "DST" in modes else 0)
@@ -195,7 +201,8 @@ class CoreEmu:
         self.v[dr] = r.astype(np.float32)
 
     def _div_op(self, op, args, dr, src):
-        """The instructions of the division handlers.  The scaling that
+        """The instructions of the division and classification handlers
+        (compares into vcc or s[80:81], selects).  The scaling that
         v_div_scale / v_div_fmas apply near the ends of the exponent range is
         not modelled: the scale flag stays clear, and v_div_fixup gives the
         IEEE quotient wherever an operand or the result is zero, infinite,
@@ -223,10 +230,17 @@ class CoreEmu:
                 ieee = (num.astype(f64) / den.astype(f64)).astype(np.float32)
                 big = lambda x: ~np.isfinite(x) | (x == 0) | (np.abs(x) > 2.0 ** 60) | (np.abs(x) < 2.0 ** -60)
                 self.v[dr] = np.where(big(num) | big(den) | big(q), ieee, q)
-            elif op == "v_cmp_nlt_f32_e64":
+            elif op.startswith("v_cmp_"):
                 a, b = src(*args[1], "SRC0"), src(*args[2], "SRC1")
-                self.vcc = ~(a < b)
-            elif op == "v_cndmask_b32_e32":
+                rel = op.split("_")[2]
+                m = {"nlt": ~(a < b), "gt": a > b, "lt": a < b, "eq": a == b, "neq": ~(a == b)}[rel]
+                if dr == "sp":
+                    assert args[0][1] == 80
+                    self.smask = m
+                else:
+                    self.vcc = m
+            elif op in ("v_cndmask_b32_e32", "v_cndmask_b32_e64"):
+                assert args[-1][0] == "vcc"
                 a, b = src(*args[1], "SRC0"), src(*args[2], "SRC1")
                 self.v[dr] = np.where(self.vcc, b, a)
             else:
@@ -291,7 +305,8 @@ class CoreEmu:
 
 
 DIV_OPS = ("v_div_scale_f32", "v_rcp_f32_e32", "v_fma_f32", "v_div_fmas_f32", "v_fmac_f32_e32", "v_div_fixup_f32",
-           "v_cmp_nlt_f32_e64", "v_cndmask_b32_e32")
+           "v_cmp_nlt_f32_e64", "v_cndmask_b32_e32", "v_cndmask_b32_e64") + tuple(
+    "v_cmp_%s_f32_%s" % (r, e) for r in ("gt", "lt", "eq", "neq") for e in ("e32", "e64"))
 
 
 def _same(a, b):
@@ -398,6 +413,45 @@ def test_core_division_forms(vi):
         assert _same(got, ref).all()
         hk = handler_kinds(words)
         assert not any(kind == gen_core.K["EXIT"] and (pay >> 24) & 15 == synth.PDIV for kind, pay in hk)
+
+
+@pytest.mark.parametrize("vi", [0] + [i for i, v in enumerate(gen_core.VARIANTS) if v[4] in (1, 3, 4)][:3])
+def test_core_classification_forms(vi):
+    """>, <, ==, AND, OR and IF run in the core in every operand form (two
+    stack or feature operands, a constant on either side), with signed
+    zeros, NaN and equal operands among the cases; only a function of two
+    constants leaves the core.  Results are the oracle's bits."""
+    T, D, NF, NCV, mode = gen_core.VARIANTS[vi]
+    F = 3
+    exprs = []
+    for f in (">", "<", "==", "and", "or"):
+        exprs += ["(%s x0 x1)" % f, "(%s x1 x0)" % f, "(%s (+ x0 x2) (* x1 x2))" % f, "(%s x2 0.5)" % f,
+                  "(%s -0.0 x1)" % f, "(%s (- x0 x1) 0)" % f, "(%s 2 (* x0 x2))" % f, "(%s x0 x0)" % f]
+    exprs += ["(if x0 x1 x2)", "(if (> x0 x1) (* x2 3) -1.5)", "(if 0 x0 x1)", "(if (and x0 x1) (or x1 x2) (== x0 x2))",
+              "(if (if x0 x1 x2) (if x2 x1 x0) (+ x0 (if x1 1 2)))", "(> 1 2)"]
+    from tests import progs
+    pop = progs.pop(*exprs)
+    rng = synth.rng_for(78)
+    X = np.round(synth.uniform_cases(rng, F, 64 * T + 19, -2, 2))
+    X[0, ::7] = -0.0
+    X[1, 1::9] = np.nan
+    X[2, 2::11] = np.inf
+    X[1, 3::5] = X[0, 3::5]
+    emu = CoreEmu(vi)
+    words, prog_off = gp.core_lower(pop, F, vi, BASE)
+    got = emu.evaluate(words, prog_off, X, F)
+    ref = oracle.tree_outputs(pop.tok, pop.cst, pop.off, X)
+    assert _same(got, ref).all(), np.argwhere(~_same(got, ref))[:4]
+    kinds = []
+    for r in words.reshape(-1, 4):
+        a = int(r[0]) | (int(r[1]) << 32)
+        slot = (a - BASE) // gen_core.SLOT
+        if a >= BASE and slot in emu.by_slot:
+            kinds.append((emu.by_slot[slot].kind & 0x7F, int(r[2])))
+    for k in ("CVV", "CVC", "CCV", "IF3"):
+        assert any(kind == gen_core.K[k] for kind, _ in kinds), k
+    leaving = [(pay >> 24) & 15 for kind, pay in kinds if kind == gen_core.K["EXIT"] and (pay >> 24) & 15 != 15]
+    assert leaving == [], leaving
 
 
 @pytest.mark.parametrize("vi", LINEAR)
