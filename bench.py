@@ -469,7 +469,8 @@ def bench_served(args):
     n_warm = max(0, min(args.warmup, args.requests - 1))
 
     def run_mode(batching, budget=0):
-        srv = gp.Server(batching=batching, memory_budget=budget)
+        srv = gp.Server(batching=batching, memory_budget=budget,
+                        hip_streams=args.hip_streams if batching else 0)
         ids = [srv.add_dataset(X, y) for X, y in data]
         lat = []
         gpop_meas = [0]
@@ -528,7 +529,7 @@ def bench_served(args):
         """Open loop: the measured requests (those after each run's warm-up)
         arrive as one Poisson stream of `rate` requests per second, taken
         round robin over the runs, whether or not earlier ones are done."""
-        srv = gp.Server(batching=batching)
+        srv = gp.Server(batching=batching, hip_streams=args.hip_streams if batching else 0)
         ids = [srv.add_dataset(X, y) for X, y in data]
         order = [(ri, k) for k in range(n_warm, args.requests) for ri in range(len(w.runs))]
         at = np.cumsum(synth.rng_for(seed).exponential(1.0 / rate, len(order)))
@@ -627,7 +628,7 @@ def bench_served(args):
                                                for k in res_a))
     config = {"workload": w.name, "n_runs": len(w.runs), "requests_per_run": args.requests,
               "warmup_requests_per_run": n_warm, "gpop_total": total_gpop, "fitness": "mse",
-              "arrivals": "closed loop, Exp(2 ms) think time"}
+              "arrivals": "closed loop, Exp(2 ms) think time", "hip_streams": args.hip_streams}
     res = base_result(args, served["gpops_per_s"], served["span_s"] / max(served["requests"], 1), config)
     res["steps"] = served["requests"]
     res["served"] = served
@@ -856,6 +857,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-arith", action="store_true", help="scale-tree: skip the {+,-,*} sub-measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--hip-streams", type=int, default=0,
+                    help="served: HIP streams for the server's two launch slots (0: one each, 1: back to back)")
     ap.add_argument("--budget-frac", type=float, default=0.0,
                     help="served: also run under a device-memory budget of this fraction of the working set")
     ap.add_argument("--requests", type=int, default=10, help="served: requests per run")

@@ -386,6 +386,10 @@ typedef struct {
                                   outputs are not written; a batch "runs" for its GP operation
                                   count divided by dry_run_gpops seconds (for testing the
                                   scheduler) */
+    int32_t hip_streams;       /* HIP streams the in-flight launches go to: launch slot k uses
+                                  stream k mod hip_streams; 0 = one per slot.  1 queues the
+                                  next launch behind the running one (no overlap on the GPU, no
+                                  idle gap while the host prepares it) */
     double dry_run_gpops;
 } gp_serve_config;
 

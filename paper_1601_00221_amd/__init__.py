@@ -379,7 +379,7 @@ class BatchConfig(C.Structure):
 class ServeConfig(C.Structure):
     _fields_ = [("memory_budget", C.c_size_t), ("max_queue", C.c_int32), ("n_streams", C.c_int32),
                 ("max_batch", C.c_int32), ("batching", C.c_int32), ("dry_run", C.c_int32),
-                ("dry_run_gpops", C.c_double)]
+                ("hip_streams", C.c_int32), ("dry_run_gpops", C.c_double)]
 
 
 class ServeStats(C.Structure):
@@ -466,9 +466,9 @@ class Server:
     """gp_serve_*: continuous-batching evaluation server."""
 
     def __init__(self, memory_budget=0, max_queue=0, n_streams=0, max_batch=0, batching=True,
-                 dry_run=False, dry_run_gpops=0.0):
+                 dry_run=False, dry_run_gpops=0.0, hip_streams=0):
         cfg = ServeConfig(memory_budget, max_queue, n_streams, max_batch, 1 if batching else 0,
-                          1 if dry_run else 0, dry_run_gpops)
+                          1 if dry_run else 0, hip_streams, dry_run_gpops)
         self._h = C.c_void_p()
         check(lib().gp_serve_create(C.byref(cfg), C.byref(self._h)))
         self._jobs = {}

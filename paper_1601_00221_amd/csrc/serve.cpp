@@ -140,7 +140,7 @@ static gp_status launch_batch(Server& S, const std::vector<gp_dataset>& ds, int 
     gp_batch_config c = default_config(refs);
     c.variant = reqs[0]->variant;
     if (c.variant < 0) return fail(GP_E_DEPTH, "no kernel variant can hold the batch");
-    hipStream_t s = S.streams[k];
+    hipStream_t s = S.streams[(size_t)k % S.streams.size()];
     gp_status st = core_ready(c.variant, s);
     if (st != GP_OK) return st;
     BatchPlan plan;
@@ -281,7 +281,9 @@ gp_status gp_serve_create(const gp_serve_config* cfg, gp_server** out) {
         S.cfg.max_batch = 1;
     }
     if (S.cfg.n_streams > 8) return fail(GP_E_INVAL, "at most 8 streams");
-    for (int i = 0; i < S.cfg.n_streams; i++) {
+    if (S.cfg.hip_streams < 0) return fail(GP_E_INVAL, "hip_streams < 0");
+    if (S.cfg.hip_streams == 0 || S.cfg.hip_streams > S.cfg.n_streams) S.cfg.hip_streams = S.cfg.n_streams;
+    for (int i = 0; i < S.cfg.hip_streams; i++) {
         hipStream_t s = nullptr;
         if (!S.cfg.dry_run) {
             hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -291,6 +293,8 @@ gp_status gp_serve_create(const gp_serve_config* cfg, gp_server** out) {
             }
         }
         S.streams.push_back(s);
+    }
+    for (int i = 0; i < S.cfg.n_streams; i++) {   // launch slots: each has its own buffers
         S.scratch.emplace_back(new BatchScratch());
         S.stream_busy.push_back(false);
     }

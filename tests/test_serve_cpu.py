@@ -124,6 +124,19 @@ def test_continuous_batching_fuses_arrivals():
     s.close()
 
 
+def test_launch_slots_on_one_hip_stream():
+    """Two launch slots sharing one HIP stream (the next batch queued behind
+    the running one) complete every request; a negative count is refused."""
+    s, ds = server(n_streams=2, hip_streams=1, max_batch=8, dry_run_gpops=5e7)
+    tickets = [s.submit(job(ds, seed=i)) for i in range(24)]
+    for t in tickets:
+        assert s.wait(t, 10_000_000) == gp.GP_OK
+    assert s.stats()["completed"] == 24
+    s.close()
+    with pytest.raises(gp.GPError):
+        gp.Server(dry_run=True, hip_streams=-1)
+
+
 def test_one_launch_per_request_baseline_mode():
     s, ds = server(batching=False, dry_run_gpops=1e9)
     tickets = [s.submit(job(ds, seed=i)) for i in range(6)]
