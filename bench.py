@@ -428,6 +428,30 @@ def bench_batched(args):
     torch.cuda.synchronize()
     unb_s = (time.perf_counter() - u0) / reps
     same = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(batched, outs))
+    # latency of each population's fitness from the start of a step: every population of the batched step is
+    # ready when its one launch ends; one launch per population finishes them one after another
+    e0 = torch.cuda.Event(enable_timing=True)
+    ends = [torch.cuda.Event(enable_timing=True) for _ in w.jobs]
+    torch.cuda.synchronize()
+    e0.record()
+    for (j, o), ev in zip(zip(w.jobs, outs), ends):
+        X, y = dd[j.dataset]
+        p = j.pop
+        if hasattr(p, "tok"):
+            gp.gp_eval_tree(p.tok, p.cst, p.off, X, y, j.kind, o)
+        else:
+            gp.gp_eval_linear(p.code, p.off, p.cst, p.cst_off, p.n_reg, X, y, j.kind, o)
+        ev.record()
+    torch.cuda.synchronize()
+    lat_unb = np.array([e0.elapsed_time(ev) for ev in ends])
+    b_ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    torch.cuda.synchronize()
+    for k in range(5):
+        b_ev[k].record()
+        gp.gp_eval_batch(dd, jobs)
+    b_ev[5].record()
+    torch.cuda.synchronize()
+    lat_b = np.array([b_ev[k].elapsed_time(b_ev[k + 1]) for k in range(5)])
     value = gpop_per_step / step_s
     log("batched %.3f ms/step (%.3f T GPop/s), one launch per population %.3f ms, identical=%s"
         % (step_s * 1e3, value / 1e12, unb_s * 1e3, same))
@@ -439,6 +463,13 @@ def bench_batched(args):
     res["unbatched"] = {"gpops_per_s": gpop_per_step / unb_s, "ms_per_step": unb_s * 1e3,
                         "launches_per_step": len(jobs), "speedup_of_batched": unb_s / step_s,
                         "fitness_identical": same}
+    # per population, from the start of a step to its fitness (batched: five steps' durations)
+    res["latency_ms"] = {"batched": {"p50": float(np.percentile(lat_b, 50)), "p99": float(np.percentile(lat_b, 99))},
+                         "unbatched": {"p50": float(np.percentile(lat_unb, 50)),
+                                       "p99": float(np.percentile(lat_unb, 99))}}
+    log("latency per population: batched p50 %.2f p99 %.2f ms, one launch per population p50 %.2f p99 %.2f ms"
+        % (res["latency_ms"]["batched"]["p50"], res["latency_ms"]["batched"]["p99"],
+           res["latency_ms"]["unbatched"]["p50"], res["latency_ms"]["unbatched"]["p99"]))
     return res
 
 
@@ -852,13 +883,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scale-tree")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-arith", action="store_true", help="scale-tree: skip the {+,-,*} sub-measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--hip-streams", type=int, default=0,
-                    help="served: HIP streams for the server's two launch slots (0: one each, 1: back to back)")
+                    help="served: HIP streams for the server's two launch slots (0: the server's default, one "
+                         "stream with launches back to back; 2: one each)")
     ap.add_argument("--budget-frac", type=float, default=0.0,
                     help="served: also run under a device-memory budget of this fraction of the working set")
     ap.add_argument("--requests", type=int, default=10, help="served: requests per run")

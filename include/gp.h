@@ -387,9 +387,10 @@ typedef struct {
                                   count divided by dry_run_gpops seconds (for testing the
                                   scheduler) */
     int32_t hip_streams;       /* HIP streams the in-flight launches go to: launch slot k uses
-                                  stream k mod hip_streams; 0 = one per slot.  1 queues the
-                                  next launch behind the running one (no overlap on the GPU, no
-                                  idle gap while the host prepares it) */
+                                  stream k mod hip_streams; 0 or 1 = one stream, so the next
+                                  launch queues behind the running one (the GPU neither idles
+                                  while the host prepares it nor splits its CUs between two
+                                  batches); n_streams = one stream per slot */
     double dry_run_gpops;
 } gp_serve_config;
 

@@ -44,63 +44,16 @@
 namespace gpx {
 #include "core_gen.inc"
 
-__device__ __forceinline__ float pdiv(float a, float b) { return (fabsf(b) < 1e-6f) ? 1.0f : a / b; }
-
-// Exit payload: byte 0 offset of A, byte 1 offset of B, byte 2 offset of the
-// destination, byte 3 = operation (low nibble) | constant flags (bit 4: A is
-// the constant, bit 5: B is the constant).  IF has a third operand: byte 2
-// is its offset, and the result goes to the lowest of the three offsets.
+// Exit payload: byte 0 offset of the operand, byte 2 offset of the
+// destination, byte 3 = operation (low nibble) | constant flag (bit 4: the
+// operand is the constant).  Only sin, cos, exp and log leave the core:
+// protected division and the classification functions have handlers.
 template <int T, int V0, bool AR>
 __device__ __forceinline__ void do_exit(uint32_t pay, uint32_t cbits, const double* tab) {
-    const uint32_t oa = pay & 255u, ob = (pay >> 8) & 255u, od = (pay >> 16) & 255u;
+    const uint32_t oa = pay & 255u, od = (pay >> 16) & 255u;
     const uint32_t op = (pay >> 24) & 15u, fl = pay >> 28;
-    // an operand is the instruction's constant (flag set) or T slots of the
+    // the operand is the instruction's constant (flag set) or T slots of the
     // core's range; one scalar branch inside the helper picks
-    if (op == OP_IF) {
-        float A[T], B[T], C[T];
-        core_gather<T, V0>(oa, A);
-        core_gather<T, V0>(ob, B);
-        core_gather<T, V0>(od, C);
-#pragma unroll
-        for (int j = 0; j < T; j++) A[j] = (A[j] != 0.0f) ? B[j] : C[j];
-        const uint32_t lo = oa < ob ? oa : ob;
-        core_scatter<T, V0>(__builtin_amdgcn_readfirstlane(lo < od ? lo : od), A);   // uniform: an SGPR
-        return;
-    }
-    if (op != GP_SIN && op != GP_COS && op != GP_EXPC && op != GP_PLOG) {
-        // the binary functions that leave the core: protected division, >, <, ==, AND, OR
-        float A[T], B[T];
-        core_gather_or_const<T, V0>(oa, fl & 1u, cbits, A);
-        core_gather_or_const<T, V0>(ob, fl & 2u, cbits, B);
-        switch (op) {
-            case GP_PDIV:
-#pragma unroll
-                for (int j = 0; j < T; j++) A[j] = pdiv(A[j], B[j]);
-                break;
-            case GP_GT:
-#pragma unroll
-                for (int j = 0; j < T; j++) A[j] = (A[j] > B[j]) ? 1.0f : 0.0f;
-                break;
-            case GP_LT:
-#pragma unroll
-                for (int j = 0; j < T; j++) A[j] = (A[j] < B[j]) ? 1.0f : 0.0f;
-                break;
-            case GP_EQ:
-#pragma unroll
-                for (int j = 0; j < T; j++) A[j] = (A[j] == B[j]) ? 1.0f : 0.0f;
-                break;
-            case GP_AND:
-#pragma unroll
-                for (int j = 0; j < T; j++) A[j] = (A[j] != 0.0f && B[j] != 0.0f) ? 1.0f : 0.0f;
-                break;
-            default:   // GP_OR
-#pragma unroll
-                for (int j = 0; j < T; j++) A[j] = (A[j] != 0.0f || B[j] != 0.0f) ? 1.0f : 0.0f;
-                break;
-        }
-        core_scatter<T, V0>(od, A);
-        return;
-    }
     float A[T];
     core_gather_or_const<T, V0>(oa, fl & 1u, cbits, A);
     if constexpr (AR) {

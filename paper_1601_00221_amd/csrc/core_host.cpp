@@ -217,26 +217,36 @@ struct Emitter {
     }
     // protected division, in the core (every arithmetic kernel has its
     // handlers): the exit's payload layout, without leaving
+    void fail_two_constants() {
+        // lowering pushes one of two constant operands first, and register programs move one into the
+        // destination: no function of two constants reaches the handlers
+        snprintf(err, 256, "internal: a function of two constants reached core translation");
+        ok = false;
+    }
     void div(int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
-        if (a_const && b_const) return exit(GP_PDIV, oa, ob, od, true, true, cst);
+        if (a_const && b_const) return fail_two_constants();
         const int kind = a_const ? CK_DCV : b_const ? CK_DVC : CK_DVV;
         put(kind, GP_PDIV, 0, 0,
             (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16), cst);
     }
     // >, <, ==, logical AND and OR in the core: 1 or 0 per slot
     void cmp(uint32_t op, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
-        if (a_const && b_const) return exit(op, oa, ob, od, true, true, cst);
+        if (a_const && b_const) return fail_two_constants();
         const int kind = a_const ? CK_CCV : b_const ? CK_CVC : CK_CVV;
         put(kind, (int)op, 0, 0,
             (uint32_t)(oa & 255) | ((uint32_t)(ob & 255) << 8) | ((uint32_t)(od & 255) << 16), cst);
     }
-    // the binary functions the arithmetic kernels apply in their own handlers (protected division and the
-    // classification functions); sin/cos/exp/log leave the core
+    // the binary functions the arithmetic kernels apply in their own handlers: protected division and the
+    // classification functions (sin/cos/exp/log are unary and leave the core)
     void apply(uint32_t op, bool boolean, int oa, int ob, int od, bool a_const, bool b_const, uint32_t cst) {
-        if (!boolean && op == GP_PDIV) div(oa, ob, od, a_const, b_const, cst);
-        else if (!boolean && (op == GP_GT || op == GP_LT || op == GP_EQ || op == GP_AND || op == GP_OR))
+        if (!boolean && op == GP_PDIV) {
+            div(oa, ob, od, a_const, b_const, cst);
+        } else if (!boolean && (op == GP_GT || op == GP_LT || op == GP_EQ || op == GP_AND || op == GP_OR)) {
             cmp(op, oa, ob, od, a_const, b_const, cst);
-        else exit(op, oa, ob, od, a_const, b_const, cst);
+        } else {
+            snprintf(err, 256, "no core handler for binary function %u", op);
+            ok = false;
+        }
     }
 };
 

@@ -29,14 +29,17 @@ T vector instructions with the wave-uniform operand offset applied through
 the gfx9 VGPR index mode (one index per instruction; the other operands of
 the handler are fixed registers, so handlers are specialised on stack level
 or register number), waits for the load and jumps to the next handler's
-address.  Every lane runs the same program, so the jump is uniform.  Work
-the core does not do itself (protected division, sin/cos/exp/log, the end
-of a program) leaves the asm block through the exit handler with the
-instruction's payload; the compiled kernel does it and re-enters.
+address.  Every lane runs the same program, so the jump is uniform.
+Protected division and the classification functions have handlers of
+their own that read their operands at any offsets.  Work the core does not
+do itself (sin/cos/exp/log, the end of a program) leaves the asm block
+through the exit handler with the instruction's payload; the compiled
+kernel does it and re-enters.
 
 Fixed SGPRs used by the block: s[60:61] code base, s62 byte offset of the
 current instruction, s63 probe flag, s[64:71] the current and next
-instruction records, s72-s74 a constant copy and index temporaries, s75 the
+instruction records, s72-s74 and s79 a constant copy and index temporaries,
+s[80:81] the division threshold or a compare's mask, vcc flags, s75 the
 end of the program's code and s78 the loads in flight for its burst load
 into the scalar cache, s[76:77] table address (probe).
 """
@@ -55,9 +58,8 @@ LIN_REGS = 8              # register slots reserved for linear programs (and sta
 # handlers or registers: a handler table half the size, and the stack
 # levels start the VGPR range), 4 like 0 for trees only (the core of mode
 # 3 with the sin/cos/exp/log code: room for many feature slots).  Work that
-# leaves the core (sin/cos/exp/log in binary64, protected division, the
-# classification functions) runs in the compiler's VGPRs: programs rich in
-# it take a variant with room for it.
+# leaves the core (sin/cos/exp/log in binary64) runs in the compiler's VGPRs:
+# programs rich in it take a variant with room for it.
 VARIANTS = [
     (8, 6, 8, 40, 0),
     (8, 6, 8, 128, 0),

@@ -98,12 +98,24 @@ gp_status Staging::begin(size_t n) {
     return GP_OK;
 }
 
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn);
+
 gp_status Staging::put(const void* src, size_t n, void* dst, hipStream_t s) {
     if (n == 0) return GP_OK;
     Half& h = half[cur];
     if (used + n > h.cap) return fail(GP_E_INVAL, "internal: staging overflow (%zu + %zu > %zu)", used, n, h.cap);
-    memcpy((char*)h.host + used, src, n);
-    hipError_t e = hipMemcpyAsync(dst, (char*)h.host + used, n, hipMemcpyHostToDevice, s);
+    char* to = (char*)h.host + used;
+    if (n >= ((size_t)1 << 22)) {
+        // a large program set: copy into the pinned buffer on the host threads, 64 KiB apiece
+        const int64_t pieces = (int64_t)((n + ((size_t)1 << 16) - 1) >> 16);
+        parallel_for(pieces, [&](int64_t i0, int64_t i1) {
+            const size_t a = (size_t)i0 << 16, b = std::min(n, (size_t)i1 << 16);
+            memcpy(to + a, (const char*)src + a, b - a);
+        });
+    } else {
+        memcpy(to, src, n);
+    }
+    hipError_t e = hipMemcpyAsync(dst, to, n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail(GP_E_DEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
     used += (n + 255) & ~(size_t)255;
     return GP_OK;

@@ -254,23 +254,13 @@ class CoreEmu:
         self.v[self.V0 + off: self.V0 + off + self.T] = vals
 
     def do_exit(self, pay, cst):
-        oa, ob, od = pay & 255, (pay >> 8) & 255, (pay >> 16) & 255
+        """sin, cos, exp or log of the operand (or the constant), as the kernel's exit computes it."""
+        oa, od = pay & 255, (pay >> 16) & 255
         op, fl = (pay >> 24) & 15, pay >> 28
+        assert op in (synth.SIN, synth.COS, synth.EXPC, synth.PLOG), op
         c = np.frombuffer(np.uint32(cst).tobytes(), np.float32)[0]
-        if op == 10:   # IF: the third operand's offset in the destination byte, result to the lowest
-            A, B, C = self.gather(oa), self.gather(ob), self.gather(od)
-            self.scatter(min(oa, ob, od), np.where(A != 0, B, C).astype(np.float32))
-            return
         A = np.full((self.T, 64), c, np.float32) if fl & 1 else self.gather(oa)
-        if op == synth.PDIV:
-            B = np.full((self.T, 64), c, np.float32) if fl & 2 else self.gather(ob)
-            with np.errstate(all="ignore"):
-                R = np.where(np.abs(B) < f32(1e-6), f32(1.0), (A / B).astype(np.float32))
-        elif op in (synth.AND, synth.OR, synth.GT, synth.LT, synth.EQ):
-            B = np.full((self.T, 64), c, np.float32) if fl & 2 else self.gather(ob)
-            R = np.vectorize(lambda x, z: oracle.apply(op, x, z), otypes=[np.float32])(A, B)
-        else:
-            R = np.vectorize(lambda x: oracle.apply(op, x), otypes=[np.float32])(A)
+        R = np.vectorize(lambda x: oracle.apply(op, x), otypes=[np.float32])(A)
         self.scatter(od, R.astype(np.float32))
 
     def evaluate(self, words, prog_off, X, n_load):
