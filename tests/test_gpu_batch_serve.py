@@ -153,12 +153,15 @@ def test_batch_rejects_bad_input():
     assert e.value.status == gp.GP_E_NOTFOUND
 
 
-@pytest.mark.parametrize("batching", [True, False])
-def test_served_results_equal_alone_and_in_the_mix(batching):
+@pytest.mark.parametrize("batching,hip_streams", [(True, 0), (True, 2), (False, 0)])
+def test_served_results_equal_alone_and_in_the_mix(batching, hip_streams):
+    """Served requests (two launches in flight queued on one HIP stream, the
+    default, or on two streams; or one launch per request) give the bits of
+    each request alone and the oracle's fitness."""
     import torch
     data = _datasets([2000, 9000, 40000], F=8, seed=11)
     dd = [(dev(X), dev(y)) for X, y in data]
-    srv = gp.Server(batching=batching, memory_budget=64 << 20)
+    srv = gp.Server(batching=batching, memory_budget=64 << 20, hip_streams=hip_streams)
     ids = [srv.add_dataset(X, y) for X, y in dd]
     rng = synth.rng_for(12)
     spec = _jobs(rng, 24, len(data))
@@ -178,7 +181,7 @@ def test_served_results_equal_alone_and_in_the_mix(batching):
         except Exception as e:  # pragma: no cover
             errors.append(e)
 
-    say("serve batching=%s" % batching)
+    say("serve batching=%s hip_streams=%d" % (batching, hip_streams))
     th = [threading.Thread(target=client, args=(i,)) for i in range(4)]
     for x in th:
         x.start()
