@@ -113,9 +113,12 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
         return (v.arith == 3) * 400000000 + mode_no_transc(v.arith) * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 -
                v.nf * 100 - v.n / 100;
     };
-    // Boolean programs: the most slots in flight per SIMD (waves x tile width)
-    // (ties: more VGPRs for the compiled code, then fewer feature slots)
-    auto score_bool = [&](const CoreVariantDesc& v) { return waves(v) * v.t * 100000 + v.ncv * 100 - v.nf; };
+    // Boolean programs: the most slots in flight per SIMD (waves x tile width); ties go to more waves (they
+    // hide the dispatch chain of the one-instruction handlers: measured 5 % on the 20-multiplexer), then to
+    // more VGPRs for the compiled code, then to fewer feature slots
+    auto score_bool = [&](const CoreVariantDesc& v) {
+        return waves(v) * v.t * 100000 + waves(v) * 1000 + v.ncv * 10 - v.nf;
+    };
     for (int i = 0; i < core_variants(); i++) {
         const CoreVariantDesc& v = kCoreVariants[i];
         if ((v.arith == 2) != boolean) continue;
