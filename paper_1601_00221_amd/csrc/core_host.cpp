@@ -109,9 +109,11 @@ int pick_core_variant(int n_load, int depth, double transc_frac, bool has_transc
     };
     auto score = [&](const CoreVariantDesc& v) {
         if (heavy) return (v.ncv >= 64) * 100000000 + waves(v) * 1000000 + v.t * 10000 - v.nf * 100 - v.n / 100;
-        // trees-only kernels first (the smallest handler tables), then those without sin/cos/exp/log code
-        return (v.arith == 3) * 400000000 + mode_no_transc(v.arith) * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 -
-               v.nf * 100 - v.n / 100;
+        // trees-only kernels first (the smallest handler tables), then those without sin/cos/exp/log code, the
+        // widest tile, then the most waves per SIMD (4 against 3 at T = 4: 13-16 % on the linear and Shuttle-shaped
+        // workloads)
+        return (v.arith == 3) * 400000000 + mode_no_transc(v.arith) * 200000000 + (v.ncv <= 64) * 100000000 + v.t * 10000 +
+               waves(v) * 1000 - v.nf * 100 - v.n / 100;
     };
     // Boolean programs: the most slots in flight per SIMD (waves x tile width); ties go to more waves (they
     // hide the dispatch chain of the one-instruction handlers: measured 5 % on the 20-multiplexer), then to

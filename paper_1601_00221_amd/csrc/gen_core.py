@@ -93,6 +93,11 @@ VARIANTS = [
     # Boolean, 4 waves per SIMD: 5 % faster than (8, 6, 20, 48) on the 20-multiplexer (2 waves, the same 16
     # slots per SIMD); 3-wave forms of it were slower
     (4, 6, 20, 24, 2),
+    # 4 waves per SIMD at T = 4 for the functions that stay in the core: the Shuttle shape's 9 inputs (16 %
+    # faster than (4, 8, 16, 48) with 3 waves) and register programs over 16 features (13 % faster than
+    # (4, 8, 16, 40))
+    (4, 8, 12, 48, 3),
+    (4, 8, 16, 32, 1),
 ]
 
 
