@@ -119,7 +119,7 @@ gp_status plan_batch(const std::vector<BatchJobRef>& jobs, const std::vector<gp_
                 if (qr[g].first == qr[g].second) continue;
                 UnitDesc u{(uint32_t)ji, (uint32_t)t, qr[g].first, qr[g].second};
                 // every slot of a tile is interpreted, ragged or not; add the tile load
-                units.push_back({gcost[g] + 4.0 * pd.n_load, u});
+                units.push_back({gcost[g] + 8.0 * pd.n_load, u});
             }
         }
         JobDesc jd;

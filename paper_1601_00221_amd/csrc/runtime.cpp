@@ -234,15 +234,21 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
 // ---------------------------------------------------------------------------
 // Program building
 // ---------------------------------------------------------------------------
-// Relative cost of one instruction, used only to balance program groups.
-static uint32_t op_cost(uint32_t op) {
+// Relative cost of one instruction, used only to balance program groups:
+// the vector instructions it issues per slot, plus one for its dispatch.
+// Protected division (about 15 per slot), the compares, IF and AND/OR (a
+// compare or two and a select) run in the core; sin/cos/exp/log are exits to
+// binary64 code of some 34 (sin, cos) or 24 (exp, log) per value.  Every
+// Boolean function is one bitwise instruction per slot.
+static uint32_t op_cost(uint32_t op, int opset) {
+    if (opset == OPSET_BOOL) return 2;
     switch (op) {
-        case GP_PDIV: return 12;
-        case GP_AND: case GP_OR: case GP_GT: case GP_LT: case GP_EQ: return 10;   // exits of a few instructions
-        case OP_IF: return 12;
-        case GP_SIN: case GP_COS: return 40;
-        case GP_EXPC: case GP_PLOG: return 24;
-        default: return 1;
+        case GP_PDIV: return 16;
+        case GP_GT: case GP_LT: case GP_EQ: case OP_IF: return 3;
+        case GP_AND: case GP_OR: return 4;
+        case GP_SIN: case GP_COS: return 35;
+        case GP_EXPC: case GP_PLOG: return 25;
+        default: return 2;
     }
 }
 
@@ -293,11 +299,11 @@ gp_status build_tree(const int32_t* tok, const float* cst, const int64_t* off, i
             int32_t nt = 0;
             for (int32_t i = 0; i < lst[p].n_instr; i++) {
                 const uint32_t op = words[2 * i] & 15u;
-                cost += op_cost(op);
-                nt += (op >= GP_SIN && op <= GP_PLOG);
+                cost += op_cost(op, opset);
+                nt += opset != OPSET_BOOL && op >= GP_SIN && op <= GP_PLOG;
             }
             ptransc[p] = nt;
-            pd.cost[p] = cost + 8;
+            pd.cost[p] = cost + 16;
         }
     });
     int32_t max_feat = -1;
@@ -370,7 +376,7 @@ gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cs
         for (int64_t i = 0; i < n; i++) {
             const uint32_t wd = src[i];
             const int op = wd & 0xFF;
-            cost += op_cost(op);
+            cost += op_cost(op, OPSET_REAL);
             const bool unary = op >= GP_SIN && op <= GP_PLOG;
             pd.n_transc += unary;
             const int na = unary ? 1 : 2;
@@ -388,7 +394,7 @@ gp_status build_linear(const uint32_t* code, const int64_t* off, const float* cs
         d.reserved0 = 0;
         d.reserved1 = 0;
         d.row = (uint64_t)p;
-        pd.cost[p] = cost + 8;
+        pd.cost[p] = cost + 16;
         pd.n_instr += n;
         pd.n_gpop += n;
         w += n + nc;
@@ -511,12 +517,15 @@ int32_t code_prefetch() {
 }
 
 static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOptions* opt, int32_t force_G = 0) {
-    // Program groups of about 1024 core instructions when over a fifth of them are sin/cos/exp/log
-    // (the exits' compiled code dominates), else 4096 (measured on the 4096-program workloads: 1-2 %
-    // better than 2048 either way).
-    const bool heavy = pd.n_instr > 0 && 5 * pd.n_transc > pd.n_instr;
+    // Program groups of about 1024 core instructions when the programs read at most 12 features, else
+    // 4096: every wave loads the features of its tile before it runs its group, and a longer group
+    // spreads those loads over more instructions.  Measured on the 4096-program workloads (kernel
+    // time, 4096 against 1024): 8-feature trees 7 % (sin/cos/exp/log) and 1.5 % (+, -, *, /) slower,
+    // 9-feature classification trees 2.7 % slower; 16-feature linear programs 2 %, 20-input
+    // multiplexer trees 2.4 % and 41-feature classification trees 6 % faster.
+    const bool few_feat = pd.n_load <= 12;
     const int32_t group_instr =
-        opt && opt->group_instr > 0 ? opt->group_instr : env_int("GP2D_GROUP_INSTR", heavy ? 1024 : 4096);
+        opt && opt->group_instr > 0 ? opt->group_instr : env_int("GP2D_GROUP_INSTR", few_feat ? 1024 : 4096);
     const int32_t target_blocks = opt && opt->target_blocks > 0 ? opt->target_blocks : env_int("GP2D_TARGET_BLOCKS", 4096);
     int64_t G = (pd.n_instr + group_instr - 1) / group_instr;
     if (((G + 3) / 4) * tiles < target_blocks) G = 4 * ((target_blocks + tiles - 1) / tiles);
