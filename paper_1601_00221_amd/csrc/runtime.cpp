@@ -520,7 +520,7 @@ static LaunchShape launch_shape(const ProgData& pd, int32_t tiles, const EvalOpt
     // Program groups of about 1024 core instructions when the programs read at most 12 features, else
     // 4096: every wave loads the features of its tile before it runs its group, and a longer group
     // spreads those loads over more instructions.  Measured on the 4096-program workloads (kernel
-    // time, 4096 against 1024): 8-feature trees 7 % (sin/cos/exp/log) and 1.5 % (+, -, *, /) slower,
+    // time, 4096 against 1024): 8-feature trees 7 % (sin/cos/exp/log) and 1.5 % (+, -, *) slower,
     // 9-feature classification trees 2.7 % slower; 16-feature linear programs 2 %, 20-input
     // multiplexer trees 2.4 % and 41-feature classification trees 6 % faster.
     const bool few_feat = pd.n_load <= 12;
@@ -586,6 +586,18 @@ int default_variant(const ProgData& pd) {
                              pd.n_transc > 0, pd.opset == OPSET_BOOL, pd.form == FORM_TREE);
 }
 
+// The variant an evaluation without an explicit one launches: GP2D_VARIANT
+// (tuning: a kernel variant index + 1) when that variant can hold the
+// programs, else the default.
+static int tuned_variant(const ProgData& pd) {
+    const int32_t ev = env_int("GP2D_VARIANT", 0) - 1;
+    if (ev >= 0 && ev < core_variants() && core_variant_nf(ev) >= pd.n_load && core_variant_d(ev) >= pd.max_depth &&
+        !(core_variant_arith(ev) && pd.n_transc > 0) && core_variant_bool(ev) == (pd.opset == OPSET_BOOL) &&
+        !(core_variant_trees_only(ev) && pd.form != FORM_TREE))
+        return ev;
+    return default_variant(pd);
+}
+
 gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh, const float* X, int32_t n_feat,
                     int64_t N, const float* y, int32_t kind, void* out, hipStream_t s, Workspace* w,
                     const EvalOptions* opt, int64_t n_bits) {
@@ -602,15 +614,9 @@ gp_status eval_core(const ProgData& pd, std::map<int, DevProgs>& dps, bool fresh
     if (boolean != (n_bits > 0)) return fail(GP_E_INVAL, "internal: Boolean programs need a bit count");
     if (boolean && kind != GP_FIT_HITS && kind != GP_OUT_CASES)
         return fail(GP_E_INVAL, "Boolean programs take GP_FIT_HITS or GP_OUT_CASES, not kind %d", kind);
-    int vi = opt && opt->variant >= 0 ? opt->variant : default_variant(pd);
-    if (!(opt && opt->variant >= 0) && !(opt && opt->no_alloc)) {
-        // GP2D_VARIANT (tuning): a kernel variant index to use instead, if it can hold the programs
-        const int32_t ev = env_int("GP2D_VARIANT", 0) - 1;
-        if (ev >= 0 && ev < core_variants() && core_variant_nf(ev) >= pd.n_load && core_variant_d(ev) >= pd.max_depth &&
-            !(core_variant_arith(ev) && pd.n_transc > 0) && core_variant_bool(ev) == (pd.opset == OPSET_BOOL) &&
-            !(core_variant_trees_only(ev) && pd.form != FORM_TREE))
-            vi = ev;
-    }
+    const int vi = opt && opt->variant >= 0 ? opt->variant
+                   : opt && opt->no_alloc   ? default_variant(pd)
+                                            : tuned_variant(pd);
     if (vi < 0 || vi >= core_variants())
         return fail(GP_E_DEPTH, "no kernel variant for %d features and depth %d", pd.n_load, pd.max_depth);
     if (core_variant_nf(vi) < pd.n_load || core_variant_d(vi) < pd.max_depth ||
@@ -866,7 +872,7 @@ gp_status gp_progset_get_info(const gp_progset* ps, gp_progset_info* info) {
     info->max_depth = ps->pd.max_depth;
     info->n_instr = ps->pd.n_instr;
     info->n_gpop = ps->pd.n_gpop;
-    info->variant = default_variant(ps->pd);
+    info->variant = tuned_variant(ps->pd);
     info->pad = 0;
     return GP_OK;
 }
