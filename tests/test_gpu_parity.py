@@ -412,3 +412,36 @@ def test_launch_shapes_give_identical_results(form, monkeypatch):
         assert np.array_equal(got.view(np.int32), ref.view(np.int32))
         assert same_bits(cases, ref_cases).all()
     torch.cuda.synchronize()
+
+
+def test_forced_variant_is_the_one_reported_and_run(monkeypatch):
+    """GP2D_VARIANT (tuning) makes a program set run another kernel variant
+    that can hold its programs; the set reports that variant, and fitness
+    still matches the oracle.  A value naming no variant leaves the default."""
+    import torch
+    rng = synth.rng_for(37)
+    F, N = 8, 512 * 5 + 77
+    pop = synth.ptc2_population(rng, 120, synth.ARITH3, F, 1, 100, 0.2)
+    X = synth.uniform_cases(rng, F, N, -2, 2)
+    y = synth.gaussian_noise(rng, N, 1.0)
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    ref = oracle.eval_tree(pop.tok, pop.cst, pop.off, X, y, "sum_abs")
+    monkeypatch.delenv("GP2D_VARIANT", raising=False)
+    ps = gp.ProgSet.tree(pop.tok, pop.cst, pop.off, F)
+    info = ps.info()
+    base = info["variant"]
+    vs = gp.variants()
+    alt = [i for i, v in enumerate(vs)
+           if i != base and not v["boolean"] and v["n_feat"] >= F and v["depth"] >= info["max_depth"]]
+    assert alt
+    for vi in sorted({alt[0], alt[-1]}):
+        monkeypatch.setenv("GP2D_VARIANT", str(vi + 1))
+        assert ps.info()["variant"] == vi
+        o = gp.out_tensor("sum_abs", pop.n_prog, N)
+        say("forced variant %d (%s)" % (vi, vs[vi]["kernel"]))
+        ps.eval(Xd, yd, "sum_abs", o)
+        torch.cuda.synchronize()
+        assert fitness_close(o.cpu().numpy(), ref).all()
+    monkeypatch.setenv("GP2D_VARIANT", str(len(vs) + 1))
+    assert ps.info()["variant"] == base
+    ps.close()
